@@ -1,0 +1,279 @@
+"""CPU FP64 oracle of the PIC step -- TEST INFRASTRUCTURE, not product code.
+
+Thin ctypes wrapper around ``liborc.so`` (built from ``pic_oracle.c``).  Only
+the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library: the two meet
+only through NumPy arrays.
+
+The stepping semantics (Section 2 of arXiv:1608.01009 gives the stage order;
+Section 4.3 the supercell grouping):
+
+* ``load_particles`` stores the particles and stable-sorts them by the
+  supercell key; the rebin counter restarts.
+* ``step`` clears J, runs the particle loop of every species in array order
+  (gather, Boris, advance, deposit, wrap), applies the Yee update, and after
+  every ``R``-th step since the last sort stable-sorts every species again.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.environ.get("PIC_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
+_lib = None
+
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+
+
+class OrcGrid(C.Structure):
+    _fields_ = [("n", C.c_int64 * 3), ("dx", C.c_double * 3), ("dt", C.c_double),
+                ("S", C.c_int64)]
+
+
+def lib():
+    """Load (building first if needed) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        G = C.POINTER(OrcGrid)
+        PP6 = _D * 6
+        PP3 = _D * 3
+        L.orc_gather.argtypes = [G, PP6, _D, _D]
+        L.orc_boris.argtypes = [C.c_double, C.c_double, C.c_double, _D, _D]
+        L.orc_advance.argtypes = [G, _D, _D, _D]
+        L.orc_deposit_vb.argtypes = [G, PP3, _D, _D, C.c_double]
+        L.orc_wrap.argtypes = [G, _D]
+        L.orc_fdtd.argtypes = [G, PP3, PP3, PP3]
+        L.orc_sort_key.argtypes = [G, _D]
+        L.orc_sort_key.restype = C.c_int64
+        L.orc_rebin.argtypes = [G, C.c_int64, _D, _D, _D, _D, _D, _D, _I64]
+        L.orc_push_deposit.argtypes = [G, C.c_double, C.c_double, C.c_double, C.c_int64,
+                                       _D, _D, _D, _D, _D, _D, PP6, PP3]
+        L.orc_rho.argtypes = [G, C.c_double, C.c_double, C.c_int64, _D, _D, _D, _D]
+        L.orc_gauss.argtypes = [G, PP3, _D, _D]
+        L.orc_divb.argtypes = [G, PP3, _D]
+        L.orc_kinetic.argtypes = [C.c_double, C.c_double, C.c_int64, _D, _D, _D]
+        L.orc_kinetic.restype = C.c_double
+        L.orc_field_energy.argtypes = [G, C.POINTER(_D), C.c_int]
+        L.orc_field_energy.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _ip(a: np.ndarray):
+    assert a.dtype == np.int64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_I64)
+
+
+def _ptrs(arrs):
+    return (_D * len(arrs))(*[_dp(a) for a in arrs])
+
+
+def make_grid(n, dx=(1.0, 1.0, 1.0), dt=None, S=1) -> OrcGrid:
+    g = OrcGrid()
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.dx[d] = float(dx[d])
+    g.dt = float(dt)
+    g.S = int(S)
+    return g
+
+
+# ---- per-particle primitives (for the pins) --------------------------------
+
+def gather(g: OrcGrid, EB, xp):
+    EB = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in EB]
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    out = np.zeros(6)
+    lib().orc_gather(C.byref(g), _ptrs(EB), _dp(xp), _dp(out))
+    return out
+
+
+def boris(q, m, dt, EB, u):
+    EB = np.ascontiguousarray(EB, dtype=np.float64)
+    u = np.array(u, dtype=np.float64)
+    lib().orc_boris(q, m, dt, _dp(EB), _dp(u))
+    return u
+
+
+def advance(g: OrcGrid, u, x):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_advance(C.byref(g), _dp(u), _dp(x), _dp(out))
+    return out
+
+
+def wrap(g: OrcGrid, x):
+    x = np.array(x, dtype=np.float64)
+    lib().orc_wrap(C.byref(g), _dp(x))
+    return x
+
+
+def deposit_vb(g: OrcGrid, J, x0, x1, qw):
+    """Accumulate one move into J (list of three flat arrays), in place."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    x1 = np.ascontiguousarray(x1, dtype=np.float64)
+    lib().orc_deposit_vb(C.byref(g), _ptrs(J), _dp(x0), _dp(x1), float(qw))
+
+
+def fdtd(g: OrcGrid, E, B, J):
+    lib().orc_fdtd(C.byref(g), _ptrs(E), _ptrs(B), _ptrs(J))
+
+
+def sort_key(g: OrcGrid, x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return int(lib().orc_sort_key(C.byref(g), _dp(x)))
+
+
+def rho(g: OrcGrid, q, w, x, y, z, out=None):
+    nc = g.n[0] * g.n[1] * g.n[2]
+    if out is None:
+        out = np.zeros(nc)
+    lib().orc_rho(C.byref(g), q, w, len(x), _dp(x), _dp(y), _dp(z), _dp(out))
+    return out
+
+
+def gauss(g: OrcGrid, E, rho_arr):
+    out = np.zeros_like(rho_arr)
+    lib().orc_gauss(C.byref(g), _ptrs(E), _dp(rho_arr), _dp(out))
+    return out
+
+
+def divb(g: OrcGrid, B):
+    out = np.zeros_like(B[0])
+    lib().orc_divb(C.byref(g), _ptrs(B), _dp(out))
+    return out
+
+
+# ---- whole-state simulator -------------------------------------------------
+
+FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz")
+
+
+class OracleSim:
+    """Plain FP64 PIC state advanced by the oracle.
+
+    ``species`` is a list of ``(charge, mass, weight)``.  Positions are in
+    cell units.  Field arrays are flat, x-fastest, ``n[0]*n[1]*n[2]`` long.
+    """
+
+    def __init__(self, n, dx, dt, species, S=4, R=20):
+        self.n = tuple(int(v) for v in n)
+        self.dx = tuple(float(v) for v in dx)
+        self.dt = float(dt)
+        self.S = int(S)
+        self.R = int(R)
+        self.g = make_grid(self.n, self.dx, self.dt, self.S)
+        self.species = [tuple(float(v) for v in s) for s in species]
+        nc = self.n[0] * self.n[1] * self.n[2]
+        self.F = [np.zeros(nc) for _ in range(9)]
+        self.P = [None] * len(self.species)
+        self.steps_since_sort = 0
+        self.step_count = 0
+
+    @property
+    def ncells(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+    def load_particles(self, s, x, y, z, ux, uy, uz, ids=None):
+        arrs = [np.array(a, dtype=np.float64).ravel() for a in (x, y, z, ux, uy, uz)]
+        n = len(arrs[0])
+        ids = np.arange(n, dtype=np.int64) if ids is None else np.array(ids, dtype=np.int64)
+        self.P[s] = arrs + [ids]
+        self._sort(s)
+        self.steps_since_sort = 0
+
+    def set_particles_unsorted(self, s, arrs):
+        """Install a state exactly as given (no sort); used to continue from a
+        state read back from another implementation."""
+        self.P[s] = [np.array(a, dtype=np.float64).ravel() for a in arrs[:6]] + \
+                    [np.array(arrs[6], dtype=np.int64).ravel()]
+
+    def _sort(self, s):
+        x, y, z, ux, uy, uz, ids = self.P[s]
+        lib().orc_rebin(C.byref(self.g), len(x), _dp(x), _dp(y), _dp(z), _dp(ux),
+                        _dp(uy), _dp(uz), _ip(ids))
+
+    def set_fields(self, EB):
+        for c in range(6):
+            self.F[c] = np.array(EB[c], dtype=np.float64).ravel().copy()
+        for c in range(6, 9):
+            self.F[c] = np.zeros(self.ncells)
+
+    def step(self, nsteps=1):
+        L = lib()
+        for _ in range(int(nsteps)):
+            for c in range(6, 9):
+                self.F[c][:] = 0.0
+            EB = _ptrs(self.F[:6])
+            J = _ptrs(self.F[6:9])
+            for s, (q, m, w) in enumerate(self.species):
+                if self.P[s] is None or len(self.P[s][0]) == 0:
+                    continue
+                x, y, z, ux, uy, uz, _ = self.P[s]
+                L.orc_push_deposit(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y), _dp(z),
+                                   _dp(ux), _dp(uy), _dp(uz), EB, J)
+            L.orc_fdtd(C.byref(self.g), _ptrs(self.F[0:3]), _ptrs(self.F[3:6]),
+                       _ptrs(self.F[6:9]))
+            self.step_count += 1
+            self.steps_since_sort += 1
+            if self.steps_since_sort % self.R == 0:
+                for s in range(len(self.species)):
+                    if self.P[s] is not None:
+                        self._sort(s)
+                self.steps_since_sort = 0
+
+    def fields(self):
+        return {k: self.F[i] for i, k in enumerate(FIELD_NAMES)}
+
+    def particles(self, s):
+        x, y, z, ux, uy, uz, ids = self.P[s]
+        return {"x": x, "y": y, "z": z, "ux": ux, "uy": uy, "uz": uz, "id": ids}
+
+    def rho(self):
+        out = np.zeros(self.ncells)
+        for s, (q, m, w) in enumerate(self.species):
+            if self.P[s] is None:
+                continue
+            x, y, z = self.P[s][:3]
+            rho(self.g, q, w, x, y, z, out)
+        return out
+
+    def gauss(self):
+        return gauss(self.g, self.F[0:3], self.rho())
+
+    def divb(self):
+        return divb(self.g, self.F[3:6])
+
+    def kinetic(self):
+        K = 0.0
+        for s, (q, m, w) in enumerate(self.species):
+            if self.P[s] is None:
+                continue
+            ux, uy, uz = self.P[s][3:6]
+            K += lib().orc_kinetic(m, w, len(ux), _dp(ux), _dp(uy), _dp(uz))
+        return K
+
+    def field_energy(self):
+        L = lib()
+        E = (_D * 3)(*[_dp(a) for a in self.F[0:3]])
+        B = (_D * 3)(*[_dp(a) for a in self.F[3:6]])
+        return (L.orc_field_energy(C.byref(self.g), E, 3),
+                L.orc_field_energy(C.byref(self.g), B, 3))
+
+    def total_charge(self):
+        return sum(q * w * (0 if self.P[s] is None else len(self.P[s][0]))
+                   for s, (q, m, w) in enumerate(self.species))

@@ -1,0 +1,425 @@
+/*
+ * pic_oracle.c -- TEST INFRASTRUCTURE, not product code.
+ *
+ * Plain single-threaded FP64 reference of the explicit electromagnetic PIC
+ * step of arXiv:1608.01009.  The paper names the stages (Section 2) and the
+ * schemes (Section 3: double precision, cloud-in-cell form factor,
+ * Villasenor-Buneman charge-conserving deposition) but prints no formula;
+ * every formula below is the textbook definition of the named scheme, coded
+ * directly, with no blocking, fusion or reordering.  Build with
+ * -ffp-contract=off so that every expression rounds as written.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no code with the GPU library.
+ */
+#include "pic_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Yee stagger of the six field components, in cell units (Section 2 names
+ * the field solver only; the Yee lattice is the standard staggered grid). */
+static const double STAG[6][3] = {
+    {0.5, 0.0, 0.0}, /* Ex */
+    {0.0, 0.5, 0.0}, /* Ey */
+    {0.0, 0.0, 0.5}, /* Ez */
+    {0.0, 0.5, 0.5}, /* Bx */
+    {0.5, 0.0, 0.5}, /* By */
+    {0.5, 0.5, 0.0}, /* Bz */
+};
+
+static int64_t wrapi(int64_t i, int64_t n) {
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static int64_t lin(const orc_grid* g, int64_t i, int64_t j, int64_t k) {
+    return wrapi(i, g->n[0]) + g->n[0] * (wrapi(j, g->n[1]) + g->n[1] * wrapi(k, g->n[2]));
+}
+
+/* ---------------------------------------------------------------------------
+ * Field interpolation with the cloud-in-cell form factor (Section 2 stage 2,
+ * Section 3 form factor).  Each component is interpolated trilinearly from the
+ * eight nearest points of its own staggered lattice:
+ *   xi_d = x_d - s_d, i_d = floor(xi_d), f_d = xi_d - i_d,
+ *   F_p = sum_{a,b,c in {0,1}} w_a(f_x) w_b(f_y) w_c(f_z) F[i+a, j+b, k+c],
+ *   w_0(f) = 1 - f, w_1(f) = f; summed with a outermost, c innermost.
+ * ------------------------------------------------------------------------- */
+void orc_gather(const orc_grid* g, const double* const EB[6], const double xp[3],
+                double out[6]) {
+    for (int c = 0; c < 6; ++c) {
+        int64_t i[3];
+        double f[3];
+        for (int d = 0; d < 3; ++d) {
+            double xi = xp[d] - STAG[c][d];
+            double fl = floor(xi);
+            i[d] = (int64_t)fl;
+            f[d] = xi - fl;
+        }
+        double acc = 0.0;
+        for (int a = 0; a < 2; ++a) {
+            double wa = a ? f[0] : 1.0 - f[0];
+            for (int b = 0; b < 2; ++b) {
+                double wb = b ? f[1] : 1.0 - f[1];
+                for (int cc = 0; cc < 2; ++cc) {
+                    double wc = cc ? f[2] : 1.0 - f[2];
+                    double w = (wa * wb) * wc;
+                    acc = acc + w * EB[c][lin(g, i[0] + a, i[1] + b, i[2] + cc)];
+                }
+            }
+        }
+        out[c] = acc;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Relativistic equations of motion (Section 2), advanced with the Boris
+ * scheme: half electric kick, magnetic rotation, half electric kick.
+ *   h = q dt / (2 m)
+ *   u- = u + h E;  gamma- = sqrt(1 + |u-|^2)
+ *   t = (h / gamma-) B;  s = 2 t / (1 + |t|^2)
+ *   u' = u- + u- x t;  u+ = u- + u' x s;  u_new = u+ + h E
+ * ------------------------------------------------------------------------- */
+void orc_boris(double q, double m, double dt, const double EB[6], double u[3]) {
+    const double h = (q * dt) / (2.0 * m);
+    const double* E = EB;
+    const double* B = EB + 3;
+    double um[3], t[3], s[3], up[3], upl[3];
+    for (int d = 0; d < 3; ++d) um[d] = u[d] + h * E[d];
+    double g2 = 1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]);
+    double gm = sqrt(g2);
+    double hg = h / gm;
+    for (int d = 0; d < 3; ++d) t[d] = hg * B[d];
+    double t2 = (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2];
+    double sf = 2.0 / (1.0 + t2);
+    for (int d = 0; d < 3; ++d) s[d] = sf * t[d];
+    /* u' = u- + u- x t */
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    /* u+ = u- + u' x s */
+    upl[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
+    upl[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
+    upl[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
+    for (int d = 0; d < 3; ++d) u[d] = upl[d] + h * E[d];
+}
+
+/* x*_d = x_d + ((dt/dx_d) u_d) g,  g = 1 / sqrt(1 + |u|^2); unwrapped. */
+void orc_advance(const orc_grid* g, const double u[3], const double x[3], double xs[3]) {
+    double gi = 1.0 / sqrt(1.0 + ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]));
+    for (int d = 0; d < 3; ++d) {
+        double cdt = g->dt / g->dx[d];
+        xs[d] = x[d] + (cdt * u[d]) * gi;
+    }
+}
+
+/* If x >= L subtract L, else if x < 0 add L; a result equal to L becomes 0
+ * (L and 0 are the same point of the periodic lattice). */
+void orc_wrap(const orc_grid* g, double x[3]) {
+    for (int d = 0; d < 3; ++d) {
+        double L = (double)g->n[d];
+        double v = x[d];
+        if (v >= L)
+            v = v - L;
+        else if (v < 0.0)
+            v = v + L;
+        if (v == L) v = 0.0;
+        x[d] = v;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Villasenor-Buneman charge-conserving current deposition (Section 3).
+ *
+ * The straight move x0 -> x1 is cut at every cell plane it crosses.  Inside a
+ * cell with integer corner c, a segment from A to B (local a = A - c,
+ * b = B - c, delta = b - a, mid m = (a + b)/2) carries the charge flux
+ *   Jx[c_x, c_y+beta, c_z+gam] += jc_x * delta_x * W_{beta,gam}(y, z)
+ *   W_00 = (1-m_y)(1-m_z) + dy dz/12    W_10 = m_y (1-m_z) - dy dz/12
+ *   W_01 = (1-m_y) m_z   - dy dz/12     W_11 = m_y m_z     + dy dz/12
+ * (dy, dz here the local displacements), i.e. the time integral of the
+ * velocity times the CIC transverse weights along the segment;
+ * jc_x = qw / (dt * area of the x face).  Jy and Jz follow by permuting axes.
+ *
+ * Crossing order: dimension d crosses plane p_d = max(floor x0_d, floor x1_d)
+ * at t_d = (p_d - x0_d) / (x1_d - x0_d); crossings are taken in increasing
+ * t, ties in dimension order x, y, z.  Each junction point is computed once
+ * as x0 + t_k (x1 - x0) with its crossing coordinate set to p_d exactly, and
+ * serves as the end of one segment and the start of the next.
+ * ------------------------------------------------------------------------- */
+static void vb_segment(const orc_grid* g, double* const J[3], const int64_t cell[3],
+                       const double A[3], const double B[3], const double jc[3]) {
+    double a[3], b[3], dl[3], m[3];
+    for (int d = 0; d < 3; ++d) {
+        a[d] = A[d] - (double)cell[d];
+        b[d] = B[d] - (double)cell[d];
+        dl[d] = b[d] - a[d];
+        m[d] = 0.5 * (a[d] + b[d]);
+    }
+    for (int d = 0; d < 3; ++d) {
+        int e1 = (d + 1) % 3; /* first transverse axis */
+        int e2 = (d + 2) % 3; /* second transverse axis */
+        /* the two transverse axes in increasing dimension order */
+        int p = e1 < e2 ? e1 : e2;
+        int r = e1 < e2 ? e2 : e1;
+        double cross = (dl[p] * dl[r]) / 12.0;
+        double flux = jc[d] * dl[d];
+        for (int bp = 0; bp < 2; ++bp) {
+            double wp = bp ? m[p] : 1.0 - m[p];
+            for (int br = 0; br < 2; ++br) {
+                double wr = br ? m[r] : 1.0 - m[r];
+                double W = wp * wr + ((bp == br) ? cross : -cross);
+                int64_t idx[3] = {cell[0], cell[1], cell[2]};
+                idx[p] += bp;
+                idx[r] += br;
+                J[d][lin(g, idx[0], idx[1], idx[2])] += flux * W;
+            }
+        }
+    }
+}
+
+void orc_deposit_vb(const orc_grid* g, double* const J[3], const double x0[3],
+                    const double x1[3], double qw) {
+    double jc[3];
+    for (int d = 0; d < 3; ++d) {
+        double area = g->dx[(d + 1) % 3] * g->dx[(d + 2) % 3];
+        jc[d] = qw / (g->dt * area);
+    }
+    double dv[3];
+    int64_t c0[3], c1[3];
+    for (int d = 0; d < 3; ++d) {
+        dv[d] = x1[d] - x0[d];
+        c0[d] = (int64_t)floor(x0[d]);
+        c1[d] = (int64_t)floor(x1[d]);
+    }
+    /* crossings, collected in dimension order, then stably sorted by time */
+    int nc = 0;
+    double tc[3], pc[3];
+    int dc[3];
+    for (int d = 0; d < 3; ++d) {
+        if (c1[d] != c0[d]) {
+            double p = (double)(c0[d] > c1[d] ? c0[d] : c1[d]);
+            tc[nc] = (p - x0[d]) / dv[d];
+            pc[nc] = p;
+            dc[nc] = d;
+            ++nc;
+        }
+    }
+    for (int i = 1; i < nc; ++i) { /* stable insertion sort on tc */
+        int j = i;
+        while (j > 0 && tc[j - 1] > tc[j]) {
+            double tt = tc[j]; tc[j] = tc[j - 1]; tc[j - 1] = tt;
+            double pp = pc[j]; pc[j] = pc[j - 1]; pc[j - 1] = pp;
+            int dd = dc[j]; dc[j] = dc[j - 1]; dc[j - 1] = dd;
+            --j;
+        }
+    }
+    double A[3] = {x0[0], x0[1], x0[2]};
+    int64_t cell[3] = {c0[0], c0[1], c0[2]};
+    for (int k = 0; k <= nc; ++k) {
+        double B[3];
+        if (k < nc) {
+            for (int d = 0; d < 3; ++d) B[d] = x0[d] + tc[k] * dv[d];
+            B[dc[k]] = pc[k];
+        } else {
+            for (int d = 0; d < 3; ++d) B[d] = x1[d];
+        }
+        vb_segment(g, J, cell, A, B, jc);
+        if (k < nc) {
+            for (int d = 0; d < 3; ++d) A[d] = B[d];
+            cell[dc[k]] = c1[dc[k]];
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Maxwell integration (Section 2 stage 1) with the Yee scheme, B kept at
+ * integer time levels by splitting its leapfrog update into two halves.
+ *   (curl E)_x[i,j,k] = (Ez[i,j+1,k]-Ez[i,j,k])/dy - (Ey[i,j,k+1]-Ey[i,j,k])/dz
+ *   (curl B)_x[i,j,k] = (Bz[i,j,k]-Bz[i,j-1,k])/dy - (By[i,j,k]-By[i,j,k-1])/dz
+ * and cyclic permutations.
+ * ------------------------------------------------------------------------- */
+static void half_b(const orc_grid* g, double* const E[3], double* const B[3]) {
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const double dx = g->dx[0], dy = g->dx[1], dz = g->dx[2];
+    const double hdt = 0.5 * g->dt;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = lin(g, i, j, k);
+                double cx = (E[2][lin(g, i, j + 1, k)] - E[2][c]) / dy -
+                            (E[1][lin(g, i, j, k + 1)] - E[1][c]) / dz;
+                double cy = (E[0][lin(g, i, j, k + 1)] - E[0][c]) / dz -
+                            (E[2][lin(g, i + 1, j, k)] - E[2][c]) / dx;
+                double cz = (E[1][lin(g, i + 1, j, k)] - E[1][c]) / dx -
+                            (E[0][lin(g, i, j + 1, k)] - E[0][c]) / dy;
+                B[0][c] = B[0][c] - hdt * cx;
+                B[1][c] = B[1][c] - hdt * cy;
+                B[2][c] = B[2][c] - hdt * cz;
+            }
+}
+
+static void full_e(const orc_grid* g, double* const E[3], double* const B[3],
+                   const double* const J[3]) {
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const double dx = g->dx[0], dy = g->dx[1], dz = g->dx[2];
+    const double dt = g->dt;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = lin(g, i, j, k);
+                double cx = (B[2][c] - B[2][lin(g, i, j - 1, k)]) / dy -
+                            (B[1][c] - B[1][lin(g, i, j, k - 1)]) / dz;
+                double cy = (B[0][c] - B[0][lin(g, i, j, k - 1)]) / dz -
+                            (B[2][c] - B[2][lin(g, i - 1, j, k)]) / dx;
+                double cz = (B[1][c] - B[1][lin(g, i - 1, j, k)]) / dx -
+                            (B[0][c] - B[0][lin(g, i, j - 1, k)]) / dy;
+                E[0][c] = E[0][c] + dt * (cx - J[0][c]);
+                E[1][c] = E[1][c] + dt * (cy - J[1][c]);
+                E[2][c] = E[2][c] + dt * (cz - J[2][c]);
+            }
+}
+
+void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
+              const double* const J[3]) {
+    half_b(g, E, B);
+    full_e(g, E, B, J);
+    half_b(g, E, B);
+}
+
+/* ---------------------------------------------------------------------------
+ * Per-cell particle storage grouped by supercells (Sections 3 and 4.3): the
+ * key orders particles by supercell (x-fastest over supercells), then by cell
+ * inside the supercell (x-fastest).  The rebin is a stable sort on that key.
+ * ------------------------------------------------------------------------- */
+int64_t orc_sort_key(const orc_grid* g, const double x[3]) {
+    const int64_t S = g->S;
+    int64_t c[3];
+    for (int d = 0; d < 3; ++d) c[d] = (int64_t)floor(x[d]);
+    int64_t ns0 = g->n[0] / S, ns1 = g->n[1] / S;
+    int64_t sc = c[0] / S + ns0 * (c[1] / S + ns1 * (c[2] / S));
+    int64_t loc = c[0] % S + S * (c[1] % S + S * (c[2] % S));
+    return sc * S * S * S + loc;
+}
+
+static void permute_d(double* a, const int64_t* perm, int64_t n, double* tmp) {
+    for (int64_t i = 0; i < n; ++i) tmp[i] = a[perm[i]];
+    memcpy(a, tmp, (size_t)n * sizeof(double));
+}
+
+void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
+               double* ux, double* uy, double* uz, int64_t* id) {
+    if (n <= 0) return;
+    const int64_t nkeys = g->n[0] * g->n[1] * g->n[2];
+    int64_t* key = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* cnt = (int64_t*)calloc((size_t)nkeys + 1, sizeof(int64_t));
+    int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    double* tmp = (double*)malloc((size_t)n * sizeof(double));
+    int64_t* itmp = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t p = 0; p < n; ++p) {
+        double xp[3] = {x[p], y[p], z[p]};
+        key[p] = orc_sort_key(g, xp);
+        cnt[key[p] + 1] += 1;
+    }
+    for (int64_t k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k]; /* start offsets */
+    for (int64_t p = 0; p < n; ++p) perm[cnt[key[p]]++] = p; /* input order kept */
+    permute_d(x, perm, n, tmp);
+    permute_d(y, perm, n, tmp);
+    permute_d(z, perm, n, tmp);
+    permute_d(ux, perm, n, tmp);
+    permute_d(uy, perm, n, tmp);
+    permute_d(uz, perm, n, tmp);
+    for (int64_t i = 0; i < n; ++i) itmp[i] = id[perm[i]];
+    memcpy(id, itmp, (size_t)n * sizeof(int64_t));
+    free(key); free(cnt); free(perm); free(tmp); free(itmp);
+}
+
+/* One species' particle loop for one step, in array order (Section 2: field
+ * interpolation and equations of motion form the push; the deposit follows). */
+void orc_push_deposit(const orc_grid* g, double q, double m, double w, int64_t n,
+                      double* x, double* y, double* z, double* ux, double* uy,
+                      double* uz, const double* const EB[6], double* const J[3]) {
+    const double qw = q * w;
+    for (int64_t p = 0; p < n; ++p) {
+        double x0[3] = {x[p], y[p], z[p]};
+        double u[3] = {ux[p], uy[p], uz[p]};
+        double f[6];
+        double x1[3];
+        orc_gather(g, EB, x0, f);
+        orc_boris(q, m, g->dt, f, u);
+        orc_advance(g, u, x0, x1);
+        orc_deposit_vb(g, J, x0, x1, qw);
+        orc_wrap(g, x1);
+        x[p] = x1[0]; y[p] = x1[1]; z[p] = x1[2];
+        ux[p] = u[0]; uy[p] = u[1]; uz[p] = u[2];
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics (not part of the step).
+ * ------------------------------------------------------------------------- */
+void orc_rho(const orc_grid* g, double q, double w, int64_t n, const double* x,
+             const double* y, const double* z, double* rho) {
+    const double dv = g->dx[0] * g->dx[1] * g->dx[2];
+    const double qv = (q * w) / dv;
+    for (int64_t p = 0; p < n; ++p) {
+        double xp[3] = {x[p], y[p], z[p]};
+        int64_t i[3];
+        double f[3];
+        for (int d = 0; d < 3; ++d) {
+            double fl = floor(xp[d]);
+            i[d] = (int64_t)fl;
+            f[d] = xp[d] - fl;
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    double w3 = (a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1]) *
+                                (c ? f[2] : 1.0 - f[2]);
+                    rho[lin(g, i[0] + a, i[1] + b, i[2] + c)] += qv * w3;
+                }
+    }
+}
+
+void orc_gauss(const orc_grid* g, const double* const E[3], const double* rho, double* out) {
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t c = lin(g, i, j, k);
+                double dive = (E[0][c] - E[0][lin(g, i - 1, j, k)]) / g->dx[0] +
+                              (E[1][c] - E[1][lin(g, i, j - 1, k)]) / g->dx[1] +
+                              (E[2][c] - E[2][lin(g, i, j, k - 1)]) / g->dx[2];
+                out[c] = dive - rho[c];
+            }
+}
+
+void orc_divb(const orc_grid* g, const double* const B[3], double* out) {
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t c = lin(g, i, j, k);
+                out[c] = (B[0][lin(g, i + 1, j, k)] - B[0][c]) / g->dx[0] +
+                         (B[1][lin(g, i, j + 1, k)] - B[1][c]) / g->dx[1] +
+                         (B[2][lin(g, i, j, k + 1)] - B[2][c]) / g->dx[2];
+            }
+}
+
+double orc_kinetic(double m, double w, int64_t n, const double* ux, const double* uy,
+                   const double* uz) {
+    double s = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        double gam = sqrt(1.0 + ((ux[p] * ux[p] + uy[p] * uy[p]) + uz[p] * uz[p]));
+        s += gam - 1.0;
+    }
+    return w * m * s;
+}
+
+double orc_field_energy(const orc_grid* g, const double* const F[], int ncomp) {
+    const int64_t nc = g->n[0] * g->n[1] * g->n[2];
+    const double dv = g->dx[0] * g->dx[1] * g->dx[2];
+    double s = 0.0;
+    for (int c = 0; c < ncomp; ++c)
+        for (int64_t i = 0; i < nc; ++i) s += F[c][i] * F[c][i];
+    return 0.5 * s * dv;
+}

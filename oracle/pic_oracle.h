@@ -1,0 +1,99 @@
+/*
+ * pic_oracle.h -- TEST INFRASTRUCTURE, not product code.
+ *
+ * A plain, slow, single-threaded FP64 CPU implementation of one explicit
+ * electromagnetic particle-in-cell step, written from the method description
+ * of arXiv:1608.01009 (Section 2: the four stages of the PIC loop -- Maxwell
+ * integration, field interpolation, relativistic equations of motion, current
+ * deposition; Section 3: double precision, cloud-in-cell form factor,
+ * Villasenor-Buneman charge-conserving deposition; Section 4.3: supercells).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no code, header or table with the GPU
+ * library; the two meet only through arrays of numbers.
+ *
+ * Units: c = eps0 = mu0 = 1.  Positions are in cell units, x in [0, n_d).
+ * Momenta u = gamma v / c.  Fields are stored on the Yee lattice, x-fastest:
+ *   lin(i,j,k) = i + nx*(j + ny*k),
+ *   Ex (i+1/2,j,k)  Ey (i,j+1/2,k)  Ez (i,j,k+1/2)
+ *   Bx (i,j+1/2,k+1/2)  By (i+1/2,j,k+1/2)  Bz (i+1/2,j+1/2,k)
+ *   J_d at the position of E_d; charge density at nodes (i,j,k).
+ * All grid indices are periodic.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int64_t n[3];    /* cells per dimension */
+    double dx[3];    /* cell size per dimension (physical units) */
+    double dt;       /* time step */
+    int64_t S;       /* supercell edge in cells (sort key only) */
+} orc_grid;
+
+/* CIC interpolation of the six field components at one position. */
+void orc_gather(const orc_grid* g, const double* const EB[6],
+                const double xp[3], double out[6]);
+
+/* Relativistic Boris rotation: u^{n-1/2} -> u^{n+1/2} in place. */
+void orc_boris(double q, double m, double dt, const double EB[6], double u[3]);
+
+/* Straight-line position advance x* = x + (dt/dx_d) u_d / gamma (unwrapped). */
+void orc_advance(const orc_grid* g, const double u[3], const double x[3],
+                 double xs[3]);
+
+/* Villasenor-Buneman deposition of the straight move x0 -> x1 of a particle
+ * of charge qw (charge times weight) into J (three Yee arrays). */
+void orc_deposit_vb(const orc_grid* g, double* const J[3], const double x0[3],
+                    const double x1[3], double qw);
+
+/* Periodic wrap of an advanced position into [0, n_d). */
+void orc_wrap(const orc_grid* g, double x[3]);
+
+/* One Yee update: B -= dt/2 curl E; E += dt (curl B - J); B -= dt/2 curl E. */
+void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
+              const double* const J[3]);
+
+/* Sort key (supercell-major, then local cell) of one in-domain position. */
+int64_t orc_sort_key(const orc_grid* g, const double x[3]);
+
+/* Stable counting sort of n particles by orc_sort_key; permutes the six
+ * state arrays and id in place. */
+void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
+               double* ux, double* uy, double* uz, int64_t* id);
+
+/* Particle loop of one species for one step: gather, Boris, advance,
+ * deposit into J (accumulating; J is not cleared here), wrap. */
+void orc_push_deposit(const orc_grid* g, double q, double m, double w,
+                      int64_t n, double* x, double* y, double* z,
+                      double* ux, double* uy, double* uz,
+                      const double* const EB[6], double* const J[3]);
+
+/* CIC charge density at the nodes: rho += q w W(x-i)W(y-j)W(z-k) / dV. */
+void orc_rho(const orc_grid* g, double q, double w, int64_t n,
+             const double* x, const double* y, const double* z, double* rho);
+
+/* Gauss residual at the nodes: sum_d (E_d[i] - E_d[i-e_d]) / dx_d - rho. */
+void orc_gauss(const orc_grid* g, const double* const E[3], const double* rho,
+               double* out);
+
+/* Divergence of B at the cell centres. */
+void orc_divb(const orc_grid* g, const double* const B[3], double* out);
+
+/* Kinetic energy sum w m (gamma - 1) of one species. */
+double orc_kinetic(double m, double w, int64_t n, const double* ux,
+                   const double* uy, const double* uz);
+
+/* Field energy 1/2 sum F^2 dV over ncomp arrays. */
+double orc_field_energy(const orc_grid* g, const double* const F[], int ncomp);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif
