@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64 PIC step on one MI355X.
+
+Workload: the uniform thermal plasma of 64^3 cells with 50 electrons per cell
+(13,107,200 particles, v_th = 0.05 c, E/B noise 1e-3, supercells 4^3, re-sort
+every 20 steps), synthetic and seeded.  A step is the whole path: gather,
+Boris push, VB deposition (LDS tiles + atomic flush), Yee update, and the
+amortised re-sort.  The particles and fields are resident in HBM before the
+timed region starts.
+
+Prints one JSON line with the throughput (particle updates/s), the roofline
+of the dominant kernel (push+deposit, HBM-bound: algorithmic bytes per launch
+over its average duration measured with HIP events on the library's stream),
+and the oracle's throughput on the host as a reported CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle updates/s (gather+push+deposit) FP64 vs FP32-mixed; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "push_deposit_64c_50ppc_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1608_01009_amd", "csrc", "push_deposit.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_launch(nparticles: int, ncell: int) -> int:
+    """Per particle: read and write x, y, z, ux, uy, uz (2 x 48 B).  Per cell:
+    read the six E/B components and add the three J components once
+    (9 x 8 B)."""
+    return nparticles * 96 + ncell * 72
+
+
+def measured_traffic():
+    """HBM bytes per push+deposit launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    try:
+        rec = json.load(open(COUNTERS))
+        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha256") != src_hash:
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(wl, steps: int):
+    """The oracle as it stands (single-threaded C, FP64) on the host: `steps`
+    full steps of the same workload."""
+    import oracle
+    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+                         S=wl.S, R=wl.R)
+    for i, s in enumerate(wl.species):
+        o.load_particles(i, *s.arrays())
+    o.set_fields(wl.fields)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    n = wl.nparticles
+    return {"value": n * steps / dt, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full steps of the same workload ({n} particles, {wl.n[0]}^3 "
+                      f"cells), single-threaded C oracle, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the PIC step here is built and timed on a "
+              "single MI355X (multi-GPU domain decomposition is not part of this build).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1608_01009_amd import pic
+    from paper_1608_01009_amd import workloads as W
+
+    log("generating the 64^3 x 50 ppc workload")
+    wl = W.config2()
+    n = wl.nparticles
+    log(f"{n} particles; loading")
+    sim = pic.Simulation.from_workload(wl)
+    log(f"warmup {args.warmup} steps")
+    sim.step(args.warmup)
+    pic.pic_enable_timers(sim.ctx, True)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)          # returns after the stream has drained
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = pic.pic_get_timers(sim.ctx)
+    counters = sim.counters()
+    value = n * args.steps / wall
+    push_ms_avg = tm[0] / max(tm[4], 1)
+    bytes_launch = algorithmic_bytes_per_launch(n, wl.ncell)
+    achieved = bytes_launch / (push_ms_avg * 1e-3) / 1e9
+    traffic = measured_traffic()
+    log(f"wall {wall*1e3:.2f} ms for {args.steps} steps; events: push+deposit {tm[0]:.2f} ms "
+        f"({push_ms_avg*1e3:.1f} us/launch), fdtd {tm[1]:.2f} ms, sort {tm[2]:.2f} ms, "
+        f"total {tm[3]:.2f} ms; far movers {counters[0]}")
+    d = sim.diagnostics()
+    log(f"diagnostics: W_E {d[0]:.6e} W_B {d[1]:.6e} K {d[2]:.6e} Q {d[3]:.6e} "
+        f"gauss drift {d[4]:.3e} divB drift {d[5]:.3e}")
+    sim.close()
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.n), "particles_per_cell": 50,
+                   "particles": n, "supercell": wl.S, "rebin_every": wl.R, "halo": 1,
+                   "precision": "fp64"},
+        "stages_ms_per_step": {"push_deposit": tm[0] / args.steps, "fdtd": tm[1] / args.steps,
+                               "resort": tm[2] / args.steps},
+        "roofline": {"bound": "hbm", "kernel": "push_deposit_kernel<4,1>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch,
+                     "avg_launch_us": push_ms_avg * 1e3},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_steps} oracle steps")
+        rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

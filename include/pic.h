@@ -1,0 +1,144 @@
+/*
+ * pic.h -- C ABI of libpic_hip.so, an MI355X (gfx950) implementation of the
+ * explicit electromagnetic particle-in-cell step of arXiv:1608.01009.
+ *
+ * The step (Section 2 of the paper) has four stages, executed in this order
+ * for every step:
+ *   1. field interpolation: cloud-in-cell (Section 3) gather of E and B from
+ *      the staggered Yee lattice to every particle;
+ *   2. relativistic equations of motion: Boris rotation of u = gamma v / c,
+ *      then the straight-line position advance x* = x + (dt/dx_d) u_d / gamma;
+ *   3. current deposition: Villasenor-Buneman charge-conserving deposition of
+ *      the move x -> x* (Section 3), then periodic wrap of x*;
+ *   4. Maxwell integration: Yee update B -= dt/2 curl E; E += dt (curl B - J);
+ *      B -= dt/2 curl E (B kept at integer time levels).
+ * Particles are kept grouped by supercells of S^3 cells (Section 4.3) and are
+ * re-sorted (stable, by supercell then cell) every `rebin_every` steps.
+ *
+ * Units: c = eps0 = mu0 = 1.  Positions are in cell units, x_d in [0, n_d).
+ * Momenta are u = gamma v / c.  charge q in elementary charges (electron
+ * -1), mass m in electron masses, weight w = number of physical particles
+ * per macro-particle.  Field arrays are n[0]*n[1]*n[2] doubles, x fastest:
+ * lin(i,j,k) = i + n0*(j + n1*k), with the Yee positions
+ *   Ex (i+1/2,j,k)  Ey (i,j+1/2,k)  Ez (i,j,k+1/2)
+ *   Bx (i,j+1/2,k+1/2)  By (i+1/2,j,k+1/2)  Bz (i+1/2,j+1/2,k)
+ *   Jx, Jy, Jz at the positions of Ex, Ey, Ez.
+ * All boundaries are periodic.
+ *
+ * Conventions for every entry point:
+ *   - returns a pic_status; nothing throws across the ABI;
+ *   - the caller owns every array it passes; the library copies inputs and
+ *     writes outputs into caller buffers before returning;
+ *   - array pointers may be host memory or device memory of the context's
+ *     GPU (the library copies with hipMemcpyDefault);
+ *   - a context is used from one thread at a time; all device work goes on
+ *     the context's stream;
+ *   - on failure, pic_last_error(ctx) describes the cause (pic_last_error
+ *     (NULL) after a failed pic_create).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,      /* invalid argument or input values */
+    PIC_ENOMEM = -2,      /* device or host allocation failed */
+    PIC_EDEVICE = -3,     /* a HIP call failed */
+    PIC_ECAPACITY = -4,   /* more particles than the species capacity / caller buffer */
+    PIC_ENONFINITE = -5,  /* a particle state became NaN or infinite during a step */
+    PIC_ESTATE = -6       /* call order violated (e.g. step before any load) */
+} pic_status;
+
+typedef struct {
+    int32_t n[3];           /* cells per dimension; each a multiple of `supercell` */
+    int32_t supercell;      /* S: supercell edge in cells (Section 4.3); 1, 2, 4 or 8 */
+    int32_t rebin_every;    /* R >= 1: stable re-sort after every R-th step since the last sort */
+    int32_t halo;           /* h: drift margin in cells of the per-supercell LDS tiles; 0 -> 1 */
+    int32_t reserved[4];    /* must be zero */
+    void* stream;           /* hipStream_t to run on, or NULL for a library-owned stream */
+} pic_grid_t;
+
+typedef struct {
+    double charge;          /* q in elementary charges */
+    double mass;            /* m in electron masses, > 0 */
+    double weight;          /* w > 0: physical particles per macro-particle */
+    int64_t capacity;       /* maximum number of particles of this species, < 2^31 */
+} pic_species_t;
+
+/* Create a context on the current HIP device.  dx[3] > 0 are the cell sizes,
+ * dt > 0 must not exceed the Yee limit 1/sqrt(sum 1/dx_d^2).  Allocates all
+ * device memory (particles twice over for the re-sort, fields, currents,
+ * sort scratch).  Fields start at zero.  *out receives the context. */
+int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
+               const pic_species_t* species, int32_t n_species, pic_ctx** out);
+
+/* Replace the particles of one species with n particles (n <= capacity).
+ * x, y, z in [0, n_d) and finite u are required (PIC_EINVAL otherwise).
+ * id may be NULL (ids 0..n-1).  The particles are stable-sorted by
+ * (supercell, cell) and the re-sort counter restarts. */
+int pic_load_particles(pic_ctx* ctx, int32_t species, int64_t n,
+                       const double* x, const double* y, const double* z,
+                       const double* ux, const double* uy, const double* uz,
+                       const int64_t* id);
+
+/* Replace E and B (EB[0..5] = Ex, Ey, Ez, Bx, By, Bz); J is cleared. */
+int pic_set_fields(pic_ctx* ctx, const double* const EB[6]);
+
+/* Advance n_steps >= 0 steps.  Asynchronous on the context stream except for
+ * one final 4-byte read of the device error word.  PIC_ENONFINITE if a
+ * particle state became non-finite (the state is then unspecified). */
+int pic_step(pic_ctx* ctx, int32_t n_steps);
+
+/* Copy Ex, Ey, Ez, Bx, By, Bz, Jx, Jy, Jz (J of the last step) into the nine
+ * caller arrays; NULL entries are skipped. */
+int pic_get_fields(pic_ctx* ctx, double* const EBJ[9]);
+
+/* Copy the particles of one species, in the library's internal (sorted)
+ * order, with their ids.  If capacity < n, returns PIC_ECAPACITY with *n_out
+ * set to the number needed.  NULL array pointers are skipped. */
+int pic_get_particles(pic_ctx* ctx, int32_t species, int64_t capacity, int64_t* n_out,
+                      double* x, double* y, double* z,
+                      double* ux, double* uy, double* uz, int64_t* id);
+
+/* Diagnostics of the current state (not part of the timed path):
+ * out[0] W_E = 1/2 sum E^2 dV, out[1] W_B, out[2] K = sum w m (gamma - 1),
+ * out[3] total charge sum q w, out[4] max |G - G_ref| with G = div E - rho
+ * (CIC rho at the nodes), out[5] max |div B - div B_ref|, out[6] time,
+ * out[7] step count.  The references are taken at the first step or
+ * diagnostics call after the last load or set_fields. */
+int pic_diagnostics(pic_ctx* ctx, double out[8]);
+
+/* Stage timers (HIP events on the context stream), off by default.
+ * pic_enable_timers(ctx, 1) turns them on and resets them. */
+int pic_enable_timers(pic_ctx* ctx, int32_t on);
+
+/* ms[0] push+deposit (gather, Boris, advance, VB deposit into LDS tiles and
+ * their flush), ms[1] Yee update, ms[2] re-sort, ms[3] total of pic_step
+ * calls; ms[4] number of push+deposit launches, ms[5] number of steps. */
+int pic_get_timers(pic_ctx* ctx, double ms[6]);
+
+/* Counters: out[0] far movers (particles that were outside their supercell's
+ * LDS tile and took the global-memory path), out[1] re-sorts, out[2] steps,
+ * out[3] LDS bytes per push+deposit workgroup. */
+int pic_get_counters(pic_ctx* ctx, int64_t out[4]);
+
+/* Message of the last failure on ctx (or of the last failed pic_create when
+ * ctx is NULL).  Owned by the library; valid until the next call. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* Release the context and all its device memory.  NULL is ignored. */
+void pic_destroy(pic_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -196,11 +196,17 @@ class OracleSim:
         self._sort(s)
         self.steps_since_sort = 0
 
-    def set_particles_unsorted(self, s, arrs):
-        """Install a state exactly as given (no sort); used to continue from a
-        state read back from another implementation."""
-        self.P[s] = [np.array(a, dtype=np.float64).ravel() for a in arrs[:6]] + \
-                    [np.array(arrs[6], dtype=np.int64).ravel()]
+    def set_state(self, particles, EB, steps_since_sort):
+        """Install a full state exactly as given (no sort): per species the
+        arrays (x, y, z, ux, uy, uz, id) in stored order, the six E/B arrays
+        and the number of steps since the last sort.  Used to take one step
+        from a state read back from another implementation."""
+        for s, arrs in enumerate(particles):
+            self.P[s] = [np.array(a, dtype=np.float64).ravel().copy() for a in arrs[:6]] + \
+                        [np.array(arrs[6], dtype=np.int64).ravel().copy()]
+        for c in range(6):
+            self.F[c] = np.array(EB[c], dtype=np.float64).ravel().copy()
+        self.steps_since_sort = int(steps_since_sort)
 
     def _sort(self, s):
         x, y, z, ux, uy, uz, ids = self.P[s]

@@ -1,0 +1,640 @@
+// Host runtime and C ABI of libpic_hip.so (declared in include/pic.h).
+//
+// A context owns all device memory of one simulation: the SoA particle
+// arrays of every species twice over (the re-sort writes into the other
+// buffer), the supercell offsets, the six Yee field arrays, two J buffers
+// (the step deposits into one while the other keeps the previous step's J for
+// readout and is cleared by the Yee pass), the sort scratch and a device
+// error word.  All work is queued on the context's stream; pic_step waits
+// only for the final 4-byte error word.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct SpeciesState {
+    SpeciesC c;
+    int64_t capacity = 0;
+    int64_t n = 0;
+    Parts buf[2] = {};
+    int cur = 0;
+    int* sc_off = nullptr;
+    bool loaded = false;
+};
+
+enum Stage { ST_PUSH = 0, ST_FDTD = 1, ST_SORT = 2, ST_TOTAL = 3, ST_N = 4 };
+
+struct TimedRange {
+    hipEvent_t a, b;
+    int stage;
+};
+
+__global__ void iota_kernel(int64_t* id, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        id[i] = i;
+}
+
+}  // namespace
+
+struct pic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Geom g{};
+    int R = 1;
+    std::vector<SpeciesState> sp;
+    double* E[3] = {};
+    double* B[3] = {};
+    double* J[2][3] = {};
+    int jcur = 0;     // J buffer holding the last step's current
+    int jdep = 1;     // J buffer the next step deposits into (zero)
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    unsigned* d_err = nullptr;
+    unsigned long long* d_nfar = nullptr;
+    unsigned* h_err = nullptr;
+    double* rho = nullptr;
+    double* tmp = nullptr;
+    double* G0 = nullptr;
+    double* divB0 = nullptr;
+    double* d_acc = nullptr;                 // W_E, W_B, then one kinetic sum per species
+    unsigned long long* d_max = nullptr;     // 2 words
+    bool ref_dirty = true;
+    bool any_loaded = false;
+    int64_t steps = 0;
+    int steps_since_sort = 0;
+    int64_t rebins = 0;
+    bool timers = false;
+    double t_ms[ST_N] = {};
+    int64_t push_launches = 0;
+    int64_t timed_steps = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<TimedRange> ranges;
+    std::vector<void*> allocs;
+    std::string err;
+};
+
+namespace {
+
+int fail(pic_ctx* c, int code, const std::string& msg) {
+    c->err = msg;
+    return code;
+}
+
+int hip_fail(pic_ctx* c, hipError_t e, const char* what) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE;
+}
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+hipError_t dalloc(pic_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) c->allocs.push_back(*p);
+    return e;
+}
+
+void release(pic_ctx* c) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->h_err) (void)hipHostFree(c->h_err);
+    c->h_err = nullptr;
+    for (auto& r : c->ranges) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    c->ranges.clear();
+    for (auto e : c->ev_free) (void)hipEventDestroy(e);
+    c->ev_free.clear();
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    c->stream = nullptr;
+}
+
+hipEvent_t take_event(pic_ctx* c) {
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets a launch sequence with events when timers are on.
+struct Timed {
+    pic_ctx* c;
+    int stage;
+    hipEvent_t a = nullptr;
+    Timed(pic_ctx* c_, int st) : c(c_), stage(st) {
+        if (c->timers) {
+            a = take_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Timed() {
+        if (c->timers && a) {
+            hipEvent_t b = take_event(c);
+            if (b) {
+                (void)hipEventRecord(b, c->stream);
+                c->ranges.push_back({a, b, stage});
+            } else {
+                c->ev_free.push_back(a);
+            }
+        }
+    }
+};
+
+// After the stream has drained: fold recorded ranges into the totals.
+void collect_timers(pic_ctx* c) {
+    for (auto& r : c->ranges) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) c->t_ms[r.stage] += ms;
+        c->ev_free.push_back(r.a);
+        c->ev_free.push_back(r.b);
+    }
+    c->ranges.clear();
+}
+
+bool bad_ptr(const void* p, int64_t n) { return n > 0 && p == nullptr; }
+
+int sync_and_check(pic_ctx* c, bool stepping) {
+    HIPCHK(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    collect_timers(c);
+    const unsigned e = *c->h_err;
+    if (e & ERR_NONFINITE)
+        return fail(c, PIC_ENONFINITE, "a particle state became non-finite during a step");
+    if (e & ERR_BADPOS)
+        return fail(c, stepping ? PIC_ENONFINITE : PIC_EINVAL,
+                    "particle positions must be finite and inside [0, n) with finite momenta");
+    return PIC_OK;
+}
+
+int compute_refs(pic_ctx* c) {
+    const int64_t nc = c->g.ncell;
+    HIPCHK(c, launch_zero(c->rho, nc, c->stream));
+    const double dv = c->g.dx[0] * c->g.dx[1] * c->g.dx[2];
+    for (auto& s : c->sp) {
+        if (s.n == 0) continue;
+        const Parts& p = s.buf[s.cur];
+        HIPCHK(c, launch_rho(c->g, (s.c.q * s.c.w) / dv, p.x, p.y, p.z, s.n, c->rho, c->stream));
+    }
+    Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
+    HIPCHK(c, launch_gauss(c->g, f, c->rho, c->G0, c->stream));
+    HIPCHK(c, launch_divb(c->g, f, c->divB0, c->stream));
+    c->ref_dirty = false;
+    return PIC_OK;
+}
+
+int do_rebin(pic_ctx* c, SpeciesState& s) {
+    const int src = s.cur, dst = 1 - s.cur;
+    HIPCHK(c, launch_rebin(c->g, s.n, s.buf[src], s.buf[dst], s.sc_off, c->scratch, c->d_err,
+                           c->stream));
+    s.cur = dst;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
+               const pic_species_t* species, int32_t n_species, pic_ctx** out) {
+    g_create_error.clear();
+    auto bad = [](const std::string& m) {
+        g_create_error = m;
+        return PIC_EINVAL;
+    };
+    if (!out) return bad("out must not be NULL");
+    *out = nullptr;
+    if (!grid || !dx) return bad("grid and dx must not be NULL");
+    if (n_species < 1 || n_species > 64 || !species)
+        return bad("n_species must be in [1, 64] with a species array");
+    for (int r = 0; r < 4; ++r)
+        if (grid->reserved[r] != 0) return bad("reserved grid fields must be zero");
+    const int S = grid->supercell;
+    if (S < 1) return bad("supercell must be >= 1");
+    if (grid->rebin_every < 1) return bad("rebin_every must be >= 1");
+    const int h = grid->halo == 0 ? 1 : grid->halo;
+    if (!push_deposit_supported(S, h))
+        return bad("unsupported (supercell, halo) pair: the LDS tiles would not fit");
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 1) return bad("grid dimensions must be >= 1");
+        if (grid->n[d] % S != 0) return bad("every grid dimension must be a multiple of supercell");
+        ncell *= grid->n[d];
+        if (!(dx[d] > 0.0) || !std::isfinite(dx[d])) return bad("dx must be finite and > 0");
+    }
+    if (ncell >= (int64_t(1) << 31)) return bad("grid too large (>= 2^31 cells)");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return bad("dt must be finite and > 0");
+    const double lim = 1.0 / std::sqrt(1.0 / (dx[0] * dx[0]) + 1.0 / (dx[1] * dx[1]) +
+                                       1.0 / (dx[2] * dx[2]));
+    if (dt > lim * (1.0 + 1e-12)) return bad("dt exceeds the Yee (Courant) stability limit");
+    for (int s = 0; s < n_species; ++s) {
+        const pic_species_t& q = species[s];
+        if (!std::isfinite(q.charge) || !(q.mass > 0.0) || !std::isfinite(q.mass) ||
+            !(q.weight > 0.0) || !std::isfinite(q.weight))
+            return bad("species charge must be finite, mass and weight finite and > 0");
+        if (q.capacity < 0 || q.capacity >= (int64_t(1) << 31))
+            return bad("species capacity must be in [0, 2^31)");
+    }
+
+    pic_ctx* c = new (std::nothrow) pic_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return PIC_ENOMEM;
+    }
+    auto cfail = [&](int code) {
+        g_create_error = c->err;
+        release(c);
+        delete c;
+        return code;
+    };
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return cfail(hip_fail(c, e, "hipGetDevice"));
+    if (grid->stream) {
+        c->stream = (hipStream_t)grid->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return cfail(hip_fail(c, e, "hipStreamCreateWithFlags"));
+        c->own_stream = true;
+    }
+    Geom& g = c->g;
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = grid->n[d];
+        g.ns[d] = grid->n[d] / S;
+        g.dx[d] = dx[d];
+        g.cdt[d] = dt / dx[d];
+    }
+    g.ncell = (int)ncell;
+    g.S = S;
+    g.nsc = g.ns[0] * g.ns[1] * g.ns[2];
+    g.h = h;
+    g.dt = dt;
+    c->R = grid->rebin_every;
+
+    const size_t fb = (size_t)ncell * sizeof(double);
+    for (int d = 0; d < 3; ++d) {
+        if ((e = dalloc(c, (void**)&c->E[d], fb)) != hipSuccess) return cfail(hip_fail(c, e, "hipMalloc E"));
+        if ((e = dalloc(c, (void**)&c->B[d], fb)) != hipSuccess) return cfail(hip_fail(c, e, "hipMalloc B"));
+        for (int b = 0; b < 2; ++b)
+            if ((e = dalloc(c, (void**)&c->J[b][d], fb)) != hipSuccess)
+                return cfail(hip_fail(c, e, "hipMalloc J"));
+    }
+    if ((e = dalloc(c, (void**)&c->rho, fb)) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->tmp, fb)) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->G0, fb)) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->divB0, fb)) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->d_acc, (2 + 64) * sizeof(double))) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->d_max, 2 * sizeof(unsigned long long))) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->d_err, 256)) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->d_nfar, 256)) != hipSuccess)
+        return cfail(hip_fail(c, e, "hipMalloc"));
+    if ((e = hipHostMalloc((void**)&c->h_err, 256, hipHostMallocDefault)) != hipSuccess)
+        return cfail(hip_fail(c, e, "hipHostMalloc"));
+    int64_t maxcap = 0;
+    c->sp.resize(n_species);
+    for (int s = 0; s < n_species; ++s) {
+        SpeciesState& st = c->sp[s];
+        const pic_species_t& q = species[s];
+        st.c.q = q.charge;
+        st.c.m = q.mass;
+        st.c.w = q.weight;
+        st.c.hq = (q.charge * dt) / (2.0 * q.mass);
+        const double qw = q.charge * q.weight;
+        for (int d = 0; d < 3; ++d) {
+            const double area = dx[(d + 1) % 3] * dx[(d + 2) % 3];
+            st.c.jc[d] = qw / (dt * area);
+        }
+        st.capacity = q.capacity;
+        if (q.capacity > maxcap) maxcap = q.capacity;
+        const size_t pb = (size_t)q.capacity * sizeof(double);
+        for (int b = 0; b < 2; ++b) {
+            Parts& P = st.buf[b];
+            if ((e = dalloc(c, (void**)&P.x, pb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.y, pb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.z, pb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.ux, pb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.uy, pb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.uz, pb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.id, (size_t)q.capacity * sizeof(int64_t))) != hipSuccess)
+                return cfail(hip_fail(c, e, "hipMalloc particles"));
+        }
+        if ((e = dalloc(c, (void**)&st.sc_off, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess)
+            return cfail(hip_fail(c, e, "hipMalloc sc_off"));
+    }
+    c->scratch_bytes = rebin_scratch_bytes(maxcap, g);
+    if ((e = dalloc(c, &c->scratch, c->scratch_bytes)) != hipSuccess)
+        return cfail(hip_fail(c, e, "hipMalloc sort scratch"));
+    // fields, both J buffers, counters to zero
+    for (int d = 0; d < 3; ++d) {
+        if ((e = launch_zero(c->E[d], ncell, c->stream)) != hipSuccess ||
+            (e = launch_zero(c->B[d], ncell, c->stream)) != hipSuccess ||
+            (e = launch_zero(c->J[0][d], ncell, c->stream)) != hipSuccess ||
+            (e = launch_zero(c->J[1][d], ncell, c->stream)) != hipSuccess)
+            return cfail(hip_fail(c, e, "zero fields"));
+    }
+    if ((e = hipMemsetAsync(c->d_err, 0, 256, c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->d_nfar, 0, 256, c->stream)) != hipSuccess)
+        return cfail(hip_fail(c, e, "hipMemsetAsync"));
+    for (auto& st : c->sp) {
+        // no particles yet: every supercell empty
+        if ((e = launch_rebin(g, 0, st.buf[0], st.buf[1], st.sc_off, c->scratch, c->d_err,
+                              c->stream)) != hipSuccess)
+            return cfail(hip_fail(c, e, "init offsets"));
+    }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return cfail(hip_fail(c, e, "hipStreamSynchronize"));
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_load_particles(pic_ctx* c, int32_t species, int64_t n, const double* x, const double* y,
+                       const double* z, const double* ux, const double* uy, const double* uz,
+                       const int64_t* id) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (species < 0 || species >= (int)c->sp.size()) return fail(c, PIC_EINVAL, "bad species index");
+    SpeciesState& s = c->sp[species];
+    if (n < 0) return fail(c, PIC_EINVAL, "n must be >= 0");
+    if (n > s.capacity) return fail(c, PIC_ECAPACITY, "n exceeds the species capacity");
+    if (bad_ptr(x, n) || bad_ptr(y, n) || bad_ptr(z, n) || bad_ptr(ux, n) || bad_ptr(uy, n) ||
+        bad_ptr(uz, n))
+        return fail(c, PIC_EINVAL, "particle arrays must not be NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    Parts& P = s.buf[0];
+    const size_t b = (size_t)n * sizeof(double);
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(P.x, x, b, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P.y, y, b, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P.z, z, b, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P.ux, ux, b, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P.uy, uy, b, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P.uz, uz, b, hipMemcpyDefault, c->stream));
+        if (id) {
+            HIPCHK(c, hipMemcpyAsync(P.id, id, (size_t)n * sizeof(int64_t), hipMemcpyDefault,
+                                     c->stream));
+        } else {
+            int nb = (int)((n + 255) / 256);
+            if (nb > 65536) nb = 65536;
+            hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(256), 0, c->stream, P.id, n);
+            HIPCHK(c, hipGetLastError());
+        }
+    }
+    HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(unsigned), c->stream));
+    s.n = n;
+    s.cur = 0;
+    {
+        Timed t(c, ST_SORT);
+        int r = do_rebin(c, s);
+        if (r != PIC_OK) return r;
+    }
+    int r = sync_and_check(c, false);
+    if (r != PIC_OK) {
+        s.n = 0;
+        (void)launch_rebin(c->g, 0, s.buf[0], s.buf[1], s.sc_off, c->scratch, c->d_err, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        return r;
+    }
+    s.loaded = true;
+    c->any_loaded = true;
+    c->steps_since_sort = 0;
+    c->ref_dirty = true;
+    return PIC_OK;
+}
+
+int pic_set_fields(pic_ctx* c, const double* const EB[6]) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!EB) return fail(c, PIC_EINVAL, "EB must not be NULL");
+    for (int k = 0; k < 6; ++k)
+        if (!EB[k]) return fail(c, PIC_EINVAL, "EB entries must not be NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t fb = (size_t)c->g.ncell * sizeof(double);
+    for (int d = 0; d < 3; ++d) {
+        HIPCHK(c, hipMemcpyAsync(c->E[d], EB[d], fb, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->B[d], EB[3 + d], fb, hipMemcpyDefault, c->stream));
+        HIPCHK(c, launch_zero(c->J[0][d], c->g.ncell, c->stream));
+        HIPCHK(c, launch_zero(c->J[1][d], c->g.ncell, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->ref_dirty = true;
+    return PIC_OK;
+}
+
+int pic_step(pic_ctx* c, int32_t n_steps) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (n_steps < 0) return fail(c, PIC_EINVAL, "n_steps must be >= 0");
+    if (!c->any_loaded) return fail(c, PIC_ESTATE, "pic_step before any pic_load_particles");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(unsigned), c->stream));
+    if (c->ref_dirty) {
+        int r = compute_refs(c);
+        if (r != PIC_OK) return r;
+    }
+    {
+        Timed total(c, ST_TOTAL);
+        Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
+        for (int it = 0; it < n_steps; ++it) {
+            double* const* Jd = c->J[c->jdep];
+            for (auto& s : c->sp) {
+                if (s.n == 0) continue;
+                Timed t(c, ST_PUSH);
+                HIPCHK(c, launch_push_deposit(c->g, s.c, s.buf[s.cur], s.sc_off, f, Jd, c->d_err,
+                                              c->d_nfar, c->stream));
+                if (c->timers) c->push_launches++;
+            }
+            {
+                Timed t(c, ST_FDTD);
+                HIPCHK(c, launch_fdtd(c->g, f, Jd, c->J[c->jcur], c->stream));
+            }
+            c->jcur = c->jdep;
+            c->jdep = 1 - c->jdep;
+            c->steps++;
+            if (c->timers) c->timed_steps++;
+            if (++c->steps_since_sort == c->R) {
+                Timed t(c, ST_SORT);
+                for (auto& s : c->sp) {
+                    if (s.n == 0) continue;
+                    int r = do_rebin(c, s);
+                    if (r != PIC_OK) return r;
+                }
+                c->steps_since_sort = 0;
+                c->rebins++;
+            }
+        }
+    }
+    return sync_and_check(c, true);
+}
+
+int pic_get_fields(pic_ctx* c, double* const EBJ[9]) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!EBJ) return fail(c, PIC_EINVAL, "EBJ must not be NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t fb = (size_t)c->g.ncell * sizeof(double);
+    const double* src[9] = {c->E[0], c->E[1], c->E[2], c->B[0], c->B[1], c->B[2],
+                            c->J[c->jcur][0], c->J[c->jcur][1], c->J[c->jcur][2]};
+    for (int k = 0; k < 9; ++k)
+        if (EBJ[k]) HIPCHK(c, hipMemcpyAsync(EBJ[k], src[k], fb, hipMemcpyDefault, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+int pic_get_particles(pic_ctx* c, int32_t species, int64_t capacity, int64_t* n_out, double* x,
+                      double* y, double* z, double* ux, double* uy, double* uz, int64_t* id) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (species < 0 || species >= (int)c->sp.size()) return fail(c, PIC_EINVAL, "bad species index");
+    if (!n_out) return fail(c, PIC_EINVAL, "n_out must not be NULL");
+    const SpeciesState& s = c->sp[species];
+    *n_out = s.n;
+    if (capacity < s.n) return fail(c, PIC_ECAPACITY, "caller capacity is smaller than n");
+    HIPCHK(c, hipSetDevice(c->device));
+    const Parts& P = s.buf[s.cur];
+    const size_t b = (size_t)s.n * sizeof(double);
+    double* dst[6] = {x, y, z, ux, uy, uz};
+    const double* src[6] = {P.x, P.y, P.z, P.ux, P.uy, P.uz};
+    if (s.n > 0) {
+        for (int k = 0; k < 6; ++k)
+            if (dst[k]) HIPCHK(c, hipMemcpyAsync(dst[k], src[k], b, hipMemcpyDefault, c->stream));
+        if (id)
+            HIPCHK(c, hipMemcpyAsync(id, P.id, (size_t)s.n * sizeof(int64_t), hipMemcpyDefault,
+                                     c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+int pic_diagnostics(pic_ctx* c, double out[8]) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!out) return fail(c, PIC_EINVAL, "out must not be NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->ref_dirty) {
+        int r = compute_refs(c);
+        if (r != PIC_OK) return r;
+    }
+    HIPCHK(c, hipMemsetAsync(c->d_acc, 0, (2 + 64) * sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_max, 0, 2 * sizeof(unsigned long long), c->stream));
+    const int64_t nc = c->g.ncell;
+    const double* Ep[3] = {c->E[0], c->E[1], c->E[2]};
+    const double* Bp[3] = {c->B[0], c->B[1], c->B[2]};
+    HIPCHK(c, launch_sum_squares(Ep, nc, c->d_acc + 0, c->stream));
+    HIPCHK(c, launch_sum_squares(Bp, nc, c->d_acc + 1, c->stream));
+    const double dv = c->g.dx[0] * c->g.dx[1] * c->g.dx[2];
+    double qtot = 0.0;
+    for (size_t k = 0; k < c->sp.size(); ++k) {
+        const SpeciesState& s = c->sp[k];
+        qtot += s.c.q * s.c.w * (double)s.n;
+        if (s.n == 0) continue;
+        const Parts& P = s.buf[s.cur];
+        HIPCHK(c, launch_kinetic(P.ux, P.uy, P.uz, s.n, c->d_acc + 2 + k, c->stream));
+    }
+    // rho, Gauss residual and div B against the references
+    HIPCHK(c, launch_zero(c->rho, nc, c->stream));
+    for (auto& s : c->sp) {
+        if (s.n == 0) continue;
+        const Parts& P = s.buf[s.cur];
+        HIPCHK(c, launch_rho(c->g, (s.c.q * s.c.w) / dv, P.x, P.y, P.z, s.n, c->rho, c->stream));
+    }
+    Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
+    HIPCHK(c, launch_gauss(c->g, f, c->rho, c->tmp, c->stream));
+    HIPCHK(c, launch_maxabs_diff(c->tmp, c->G0, nc, c->d_max + 0, c->stream));
+    HIPCHK(c, launch_divb(c->g, f, c->tmp, c->stream));
+    HIPCHK(c, launch_maxabs_diff(c->tmp, c->divB0, nc, c->d_max + 1, c->stream));
+    double acc[2 + 64];
+    unsigned long long mx[2];
+    HIPCHK(c, hipMemcpyAsync(acc, c->d_acc, sizeof(acc), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(mx, c->d_max, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double K = 0.0;
+    for (size_t k = 0; k < c->sp.size(); ++k) K += c->sp[k].c.w * c->sp[k].c.m * acc[2 + k];
+    out[0] = 0.5 * acc[0] * dv;
+    out[1] = 0.5 * acc[1] * dv;
+    out[2] = K;
+    out[3] = qtot;
+    double g0, g1;
+    std::memcpy(&g0, &mx[0], sizeof(double));
+    std::memcpy(&g1, &mx[1], sizeof(double));
+    out[4] = g0;
+    out[5] = g1;
+    out[6] = (double)c->steps * c->g.dt;
+    out[7] = (double)c->steps;
+    return PIC_OK;
+}
+
+int pic_enable_timers(pic_ctx* c, int32_t on) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    (void)hipStreamSynchronize(c->stream);
+    collect_timers(c);
+    c->timers = on != 0;
+    for (int k = 0; k < ST_N; ++k) c->t_ms[k] = 0.0;
+    c->push_launches = 0;
+    c->timed_steps = 0;
+    return PIC_OK;
+}
+
+int pic_get_timers(pic_ctx* c, double ms[6]) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!ms) return fail(c, PIC_EINVAL, "ms must not be NULL");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    collect_timers(c);
+    ms[0] = c->t_ms[ST_PUSH];
+    ms[1] = c->t_ms[ST_FDTD];
+    ms[2] = c->t_ms[ST_SORT];
+    ms[3] = c->t_ms[ST_TOTAL];
+    ms[4] = (double)c->push_launches;
+    ms[5] = (double)c->timed_steps;
+    return PIC_OK;
+}
+
+int pic_get_counters(pic_ctx* c, int64_t out[4]) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!out) return fail(c, PIC_EINVAL, "out must not be NULL");
+    unsigned long long nfar = 0;
+    HIPCHK(c, hipMemcpyAsync(&nfar, c->d_nfar, sizeof(nfar), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out[0] = (int64_t)nfar;
+    out[1] = c->rebins;
+    out[2] = c->steps;
+    out[3] = push_deposit_lds_bytes(c->g);
+    return PIC_OK;
+}
+
+const char* pic_last_error(const pic_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+void pic_destroy(pic_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    release(c);
+    delete c;
+}
+
+}  // extern "C"

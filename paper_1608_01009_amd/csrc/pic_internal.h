@@ -1,0 +1,90 @@
+// Internal declarations shared by the HIP translation units of libpic_hip.so.
+// Device code targets gfx950 (CDNA4): wave64, 160 KiB LDS per CU, native
+// FP64 atomics in LDS (ds_add_f64) and in global memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// Device error word bits.
+enum : unsigned {
+    ERR_NONFINITE = 1u,   // a particle state became NaN / Inf during a step
+    ERR_BADPOS = 2u,      // a loaded position is outside [0, n) or not finite
+};
+
+// Geometry and constants of one context, passed by value to kernels.
+struct Geom {
+    int n[3];          // cells
+    int ncell;         // n0*n1*n2
+    int S;             // supercell edge
+    int ns[3];         // supercells per dimension
+    int nsc;           // number of supercells
+    int h;             // halo (drift margin) of the LDS tiles, cells
+    double dt;
+    double cdt[3];     // dt / dx_d
+    double dx[3];
+};
+
+// Per-species constants of the particle push.
+struct SpeciesC {
+    double q, m, w;
+    double hq;         // q dt / (2 m)
+    double jc[3];      // q w / (dt * face area of the d face)
+};
+
+// SoA particle arrays of one species (one buffer of the double buffer).
+struct Parts {
+    double* x;
+    double* y;
+    double* z;
+    double* ux;
+    double* uy;
+    double* uz;
+    int64_t* id;
+};
+
+struct Fields {
+    double* E[3];
+    double* B[3];
+};
+
+// ---- launchers (implemented in the kernel translation units) --------------
+
+// Gather + Boris + advance + VB deposit + wrap for every particle of one
+// species; deposits are accumulated into J (which must hold the sum of the
+// previous species of this step, or zero).  Returns the LDS bytes used per
+// workgroup through lds_bytes (may be NULL).
+hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p,
+                               const int* sc_off, const Fields& f, double* const J[3],
+                               unsigned* err, unsigned long long* nfar, hipStream_t s);
+int push_deposit_lds_bytes(const Geom& g);
+bool push_deposit_supported(int S, int h);
+
+// Yee update; also clears Jclear (the buffer the next step deposits into).
+hipError_t launch_fdtd(const Geom& g, const Fields& f, double* const J[3],
+                       double* const Jclear[3], hipStream_t s);
+
+// Fill n doubles with zero.
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+
+// Stable sort of one species by (supercell, cell): src -> dst, sc_off filled.
+// scratch must hold rebin_scratch_bytes(n, g) bytes.
+size_t rebin_scratch_bytes(int64_t n, const Geom& g);
+hipError_t launch_rebin(const Geom& g, int64_t n, const Parts& src, const Parts& dst,
+                        int* sc_off, void* scratch, unsigned* err, hipStream_t s);
+
+// Diagnostics.
+hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, hipStream_t s);
+hipError_t launch_kinetic(const double* ux, const double* uy, const double* uz, int64_t n,
+                          double* acc, hipStream_t s);
+hipError_t launch_rho(const Geom& g, double qv, const double* x, const double* y,
+                      const double* z, int64_t n, double* rho, hipStream_t s);
+hipError_t launch_gauss(const Geom& g, const Fields& f, const double* rho, double* out,
+                        hipStream_t s);
+hipError_t launch_divb(const Geom& g, const Fields& f, double* out, hipStream_t s);
+hipError_t launch_maxabs_diff(const double* a, const double* b, int64_t n,
+                              unsigned long long* acc_bits, hipStream_t s);
+
+}  // namespace pic

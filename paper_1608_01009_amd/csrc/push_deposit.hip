@@ -1,0 +1,448 @@
+// Particle push and current deposition for one species (stages 2-4 of the
+// PIC step of arXiv:1608.01009, Section 2: field interpolation, relativistic
+// equations of motion, current deposition).
+//
+// One workgroup per supercell (Section 4.3 groups particles by supercells so
+// that the grid data they touch stays close; here that data is staged in
+// LDS):
+//   1. the E/B values of the supercell plus an h-cell drift margin and the
+//      one-node interpolation stencil are copied into an LDS tile,
+//   2. each lane takes one particle at a time (SoA loads and stores are
+//      coalesced because particles are sorted by supercell), gathers E/B
+//      from the tile with cloud-in-cell weights, applies the Boris rotation,
+//      advances the position, splits the move at cell planes
+//      (Villasenor-Buneman) and accumulates the current of every segment
+//      into an LDS J tile with ds_add_f64,
+//   3. the J tile is added into the global J arrays with FP64 global atomics
+//      (neighbouring tiles overlap by the halo, so the adds must be atomic).
+// Particles that drifted further than the halo since the last re-sort take a
+// global-memory path (gather from global E/B, global atomics for J).
+//
+// Gather, Boris and advance are evaluated in exactly the expression order of
+// the textbook formulas with floating-point contraction off, so positions and
+// momenta are reproducible bit for bit by any IEEE FP64 evaluation of the same
+// formulas.
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X.  Map
+// them so that each XCD receives a contiguous range of supercells: the
+// overlapping halos of neighbouring tiles are then read and atomically
+// updated through the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+struct PDArgs {
+    Geom g;
+    SpeciesC sp;
+    Parts p;
+    const int* sc_off;
+    const double* EB[6];
+    double* J[3];
+    unsigned* err;
+    unsigned long long* nfar;
+};
+
+// Trilinear cloud-in-cell sum of one component in the order
+// sum_a sum_b sum_c ((w_a w_b) w_c) F[a, b, c]  (a: x, b: y, c: z).
+template <class Load>
+__device__ __forceinline__ double cic8(const Load& ld, const double wx[2], const double wy[2],
+                                       const double wz[2]) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double w = (wx[a] * wy[b]) * wz[c];
+                acc = acc + w * ld(a, b, c);
+            }
+    return acc;
+}
+
+// One straight segment A->B inside the cell with integer corner `cell`
+// (Villasenor-Buneman): for J_d, the four edges of the d-directed cell edges
+// receive jc_d * delta_d * W with W = w_p w_r +- delta_p delta_r / 12 at the
+// segment midpoint.  `sink(d, i, j, k, v)` adds v to J_d at the edge whose
+// integer corner is lattice node (i, j, k) (unwrapped).
+template <class Sink>
+__device__ __forceinline__ void vb_segment(const double A[3], const double B[3],
+                                           const int cell[3], const double jc[3],
+                                           const Sink& sink) {
+#pragma clang fp contract(off)
+    double a[3], b[3], dl[3], m[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        a[d] = A[d] - (double)cell[d];
+        b[d] = B[d] - (double)cell[d];
+        dl[d] = b[d] - a[d];
+        m[d] = 0.5 * (a[d] + b[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+        const int p = e1 < e2 ? e1 : e2;
+        const int r = e1 < e2 ? e2 : e1;
+        const double cross = (dl[p] * dl[r]) / 12.0;
+        const double flux = jc[d] * dl[d];
+#pragma unroll
+        for (int bp = 0; bp < 2; ++bp) {
+            const double wp = bp ? m[p] : 1.0 - m[p];
+#pragma unroll
+            for (int br = 0; br < 2; ++br) {
+                const double wr = br ? m[r] : 1.0 - m[r];
+                const double W = wp * wr + ((bp == br) ? cross : -cross);
+                int o[3] = {0, 0, 0};
+                o[p] = bp;
+                o[r] = br;
+                sink(d, cell[0] + o[0], cell[1] + o[1], cell[2] + o[2], flux * W);
+            }
+        }
+    }
+}
+
+// Compare-exchange of (time, dimension) pairs ordered by time, then dimension.
+__device__ __forceinline__ void cswap(double& ta, int& da, double& tb, int& db) {
+    const bool sw = (tb < ta) || (tb == ta && db < da);
+    const double t = sw ? tb : ta;
+    const int d = sw ? db : da;
+    tb = sw ? ta : tb;
+    db = sw ? da : db;
+    ta = t;
+    da = d;
+}
+
+// Split x0 -> x1 at the cell planes it crosses, in order of crossing time
+// (ties: x, y, z), and deposit every segment.  Each junction point is
+// x0 + t (x1 - x0) with its crossing coordinate set to the plane exactly.
+template <class Sink>
+__device__ __forceinline__ void vb_move(const double x0[3], const double x1[3], const int c0[3],
+                                        const int c1[3], const double jc[3], const Sink& sink) {
+#pragma clang fp contract(off)
+    double dv[3], pl[3], t[3];
+    int dm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        dv[d] = x1[d] - x0[d];
+        const int p = c0[d] > c1[d] ? c0[d] : c1[d];
+        pl[d] = (double)p;
+        t[d] = (c1[d] != c0[d]) ? (pl[d] - x0[d]) / dv[d] : __builtin_huge_val();
+        dm[d] = d;
+    }
+    const int nc = (c1[0] != c0[0]) + (c1[1] != c0[1]) + (c1[2] != c0[2]);
+    cswap(t[0], dm[0], t[1], dm[1]);
+    cswap(t[1], dm[1], t[2], dm[2]);
+    cswap(t[0], dm[0], t[1], dm[1]);
+    double A[3] = {x0[0], x0[1], x0[2]};
+    int cell[3] = {c0[0], c0[1], c0[2]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k > nc) break;
+        double B[3];
+        if (k < nc) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) B[d] = (dm[k] == d) ? pl[d] : x0[d] + t[k] * dv[d];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) B[d] = x1[d];
+        }
+        vb_segment(A, B, cell, jc, sink);
+        if (k < nc) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                A[d] = B[d];
+                if (dm[k] == d) cell[d] = c1[d];
+            }
+        }
+    }
+}
+
+// Relativistic Boris rotation, then the position advance (unwrapped).
+__device__ __forceinline__ void boris_advance(const SpeciesC& sp, const Geom& g, const double E[3],
+                                              const double Bf[3], double u[3], const double x0[3],
+                                              double x1[3]) {
+#pragma clang fp contract(off)
+    const double h = sp.hq;
+    double um[3], t[3], s[3], up[3], upl[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) um[d] = u[d] + h * E[d];
+    const double g2 = 1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]);
+    const double gm = sqrt(g2);
+    const double hg = h / gm;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) t[d] = hg * Bf[d];
+    const double tt = (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2];
+    const double sf = 2.0 / (1.0 + tt);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s[d] = sf * t[d];
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    upl[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
+    upl[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
+    upl[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = upl[d] + h * E[d];
+    const double gi = 1.0 / sqrt(1.0 + ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x1[d] = x0[d] + (g.cdt[d] * u[d]) * gi;
+}
+
+__device__ __forceinline__ double wrap_coord(double v, double L) {
+#pragma clang fp contract(off)
+    if (v >= L)
+        v = v - L;
+    else if (v < 0.0)
+        v = v + L;
+    if (v == L) v = 0.0;
+    return v;
+}
+
+// Interpolation stencil of one position: for stagger 0 and 1/2 per axis the
+// lower lattice index and the two weights (1 - f, f).
+struct Stencil {
+    int i0[3], ih[3];
+    double w0[3][2], wh[3][2];
+};
+
+__device__ __forceinline__ void make_stencil(const double x[3], const double fl[3], Stencil& st) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double f0 = x[d] - fl[d];
+        st.i0[d] = (int)fl[d];
+        st.w0[d][0] = 1.0 - f0;
+        st.w0[d][1] = f0;
+        const double xh = x[d] - 0.5;
+        const double flh = floor(xh);
+        const double fh = xh - flh;
+        st.ih[d] = (int)flh;
+        st.wh[d][0] = 1.0 - fh;
+        st.wh[d][1] = fh;
+    }
+}
+
+// Gather of the six components given a loader ld(comp, ix, iy, iz, a, b, c)
+// where (ix, iy, iz) is the lower stencil corner in the loader's frame.
+template <class Ld>
+__device__ __forceinline__ void gather6(const Stencil& st, const int off[3], const Ld& ld,
+                                        double E[3], double Bf[3]) {
+    // Yee stagger per component: Ex (h,0,0) Ey (0,h,0) Ez (0,0,h)
+    //                            Bx (0,h,h) By (h,0,h) Bz (h,h,0)
+    const int ix0 = st.i0[0] + off[0], iy0 = st.i0[1] + off[1], iz0 = st.i0[2] + off[2];
+    const int ixh = st.ih[0] + off[0], iyh = st.ih[1] + off[1], izh = st.ih[2] + off[2];
+    E[0] = cic8([&](int a, int b, int c) { return ld(0, ixh, iy0, iz0, a, b, c); },
+                st.wh[0], st.w0[1], st.w0[2]);
+    E[1] = cic8([&](int a, int b, int c) { return ld(1, ix0, iyh, iz0, a, b, c); },
+                st.w0[0], st.wh[1], st.w0[2]);
+    E[2] = cic8([&](int a, int b, int c) { return ld(2, ix0, iy0, izh, a, b, c); },
+                st.w0[0], st.w0[1], st.wh[2]);
+    Bf[0] = cic8([&](int a, int b, int c) { return ld(3, ix0, iyh, izh, a, b, c); },
+                 st.w0[0], st.wh[1], st.wh[2]);
+    Bf[1] = cic8([&](int a, int b, int c) { return ld(4, ixh, iy0, izh, a, b, c); },
+                 st.wh[0], st.w0[1], st.wh[2]);
+    Bf[2] = cic8([&](int a, int b, int c) { return ld(5, ixh, iyh, iz0, a, b, c); },
+                 st.wh[0], st.wh[1], st.w0[2]);
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c) {
+    return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+template <int S, int H>
+__global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
+    constexpr int T = S + 2 * H + 2;   // E/B tile edge in nodes
+    constexpr int T2 = T * T, T3 = T2 * T;
+    constexpr int TJ = S + 2 * H + 3;  // J tile edge in nodes
+    constexpr int TJ2 = TJ * TJ, TJ3 = TJ2 * TJ;
+    __shared__ double eb[6 * T3];
+    __shared__ double jt[3 * TJ3];
+
+    const int sc = xcd_block(blockIdx.x, gridDim.x);
+    const int p0 = a.sc_off[sc], p1 = a.sc_off[sc + 1];
+    if (p0 >= p1) return;  // empty supercell: uniform exit before any barrier
+
+    const Geom& g = a.g;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int sx = sc % g.ns[0];
+    const int syz = sc / g.ns[0];
+    const int sy = syz % g.ns[1], sz = syz / g.ns[1];
+    const int base[3] = {sx * S, sy * S, sz * S};          // first cell of the supercell
+    const int org[3] = {base[0] - H - 1, base[1] - H - 1, base[2] - H - 1};  // tile origin
+
+    for (int t = threadIdx.x; t < 6 * T3; t += kBlock) {
+        const int c = t / T3;
+        const int r = t - c * T3;
+        const int tz = r / T2, ty = (r / T) % T, tx = r % T;
+        const int gx = wrapi(org[0] + tx, nx), gy = wrapi(org[1] + ty, ny),
+                  gz = wrapi(org[2] + tz, nz);
+        eb[t] = a.EB[c][gx + nx * (gy + ny * gz)];
+    }
+    for (int t = threadIdx.x; t < 3 * TJ3; t += kBlock) jt[t] = 0.0;
+    __syncthreads();
+
+    const double L[3] = {(double)nx, (double)ny, (double)nz};
+    const int nn[3] = {nx, ny, nz};
+
+    for (int ip = p0 + (int)threadIdx.x; ip < p1; ip += kBlock) {
+        double x0[3] = {a.p.x[ip], a.p.y[ip], a.p.z[ip]};
+        double u[3] = {a.p.ux[ip], a.p.uy[ip], a.p.uz[ip]};
+        if (!(finite3(x0[0], x0[1], x0[2]) && finite3(u[0], u[1], u[2]))) {
+            atomicOr(a.err, ERR_NONFINITE);
+            continue;
+        }
+        double fl[3];
+        int c0[3], rel[3];
+        bool inside = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            fl[d] = floor(x0[d]);
+            c0[d] = (int)fl[d];
+            int r = c0[d] - base[d];
+            if (r >= S + H)
+                r -= nn[d];
+            else if (r < -H)
+                r += nn[d];
+            rel[d] = r;
+            inside = inside && (r >= -H) && (r < S + H);
+        }
+        Stencil st;
+        make_stencil(x0, fl, st);
+        double E[3], Bf[3];
+        // tile node index of cell c0 is rel + H + 1
+        int off[3];
+        if (inside) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) off[d] = rel[d] + H + 1 - c0[d];
+            gather6(st, off,
+                    [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
+                        return eb[comp * T3 + (ix + da) + T * (iy + db) + T2 * (iz + dc)];
+                    },
+                    E, Bf);
+        } else {
+            atomicAdd(a.nfar, 1ull);
+            off[0] = off[1] = off[2] = 0;
+            gather6(st, off,
+                    [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
+                        return a.EB[comp][wrapi(ix + da, nx) +
+                                          nx * (wrapi(iy + db, ny) + ny * wrapi(iz + dc, nz))];
+                    },
+                    E, Bf);
+        }
+        double x1[3];
+        boris_advance(a.sp, g, E, Bf, u, x0, x1);
+        if (!(finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]))) {
+            atomicOr(a.err, ERR_NONFINITE);
+            continue;
+        }
+        int c1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
+        if (inside) {
+            // J tile node of lattice node n is n - c0 + rel + H + 1 per axis
+            const int jo0 = rel[0] + H + 1 - c0[0], jo1 = rel[1] + H + 1 - c0[1],
+                      jo2 = rel[2] + H + 1 - c0[2];
+            vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double v) {
+                atomicAdd(&jt[d * TJ3 + (i + jo0) + TJ * (j + jo1) + TJ2 * (k + jo2)], v);
+            });
+        } else {
+            vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double v) {
+                unsafeAtomicAdd(
+                    &a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], v);
+            });
+        }
+        // positions are stored wrapped into [0, n)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x1[d] = wrap_coord(x1[d], L[d]);
+        a.p.x[ip] = x1[0];
+        a.p.y[ip] = x1[1];
+        a.p.z[ip] = x1[2];
+        a.p.ux[ip] = u[0];
+        a.p.uy[ip] = u[1];
+        a.p.uz[ip] = u[2];
+    }
+    __syncthreads();
+
+    for (int t = threadIdx.x; t < 3 * TJ3; t += kBlock) {
+        const double v = jt[t];
+        if (v != 0.0) {
+            const int c = t / TJ3;
+            const int r = t - c * TJ3;
+            const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
+            const int gx = wrapi(org[0] + tx, nx), gy = wrapi(org[1] + ty, ny),
+                      gz = wrapi(org[2] + tz, nz);
+            unsafeAtomicAdd(&a.J[c][gx + nx * (gy + ny * gz)], v);
+        }
+    }
+}
+
+template <int S, int H>
+hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
+    hipLaunchKernelGGL((push_deposit_kernel<S, H>), dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+    return hipGetLastError();
+}
+
+template <int S, int H>
+constexpr int lds_bytes_sh() {
+    return (6 * (S + 2 * H + 2) * (S + 2 * H + 2) * (S + 2 * H + 2) +
+            3 * (S + 2 * H + 3) * (S + 2 * H + 3) * (S + 2 * H + 3)) *
+           (int)sizeof(double);
+}
+
+}  // namespace
+
+// Supported (S, h) pairs: the two LDS tiles of one workgroup must fit in the
+// 64 KiB a workgroup may statically allocate.
+#define PIC_SH_TABLE(X) \
+    X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 1) X(4, 1) X(4, 2) X(5, 1) X(6, 1)
+
+bool push_deposit_supported(int S, int h) {
+#define PIC_X(s_, h_) if (S == s_ && h == h_) return true;
+    PIC_SH_TABLE(PIC_X)
+#undef PIC_X
+    return false;
+}
+
+int push_deposit_lds_bytes(const Geom& g) {
+#define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return lds_bytes_sh<s_, h_>();
+    PIC_SH_TABLE(PIC_X)
+#undef PIC_X
+    return -1;
+}
+
+hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p,
+                               const int* sc_off, const Fields& f, double* const J[3],
+                               unsigned* err, unsigned long long* nfar, hipStream_t s) {
+    PDArgs args;
+    args.g = g;
+    args.sp = sp;
+    args.p = p;
+    args.sc_off = sc_off;
+    for (int c = 0; c < 3; ++c) {
+        args.EB[c] = f.E[c];
+        args.EB[3 + c] = f.B[c];
+        args.J[c] = J[c];
+    }
+    args.err = err;
+    args.nfar = nfar;
+    if (g.nsc <= 0) return hipSuccess;
+#define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return launch_sh<s_, h_>(args, s);
+    PIC_SH_TABLE(PIC_X)
+#undef PIC_X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pic

@@ -1,0 +1,116 @@
+"""GPU <-> oracle parity of the whole step, through the C ABI.
+
+One step from an identical state (see gpu_parity_util): bit-exact ids and
+cells, x within 2 ulp, u/J/E/B within 1e-12 relative (max norm per array).
+Sizes span several supercells and a ragged tail; cases cover the rebin step,
+several species, single-supercell (self-overlapping) grids, other supercell
+and halo sizes, anisotropic cells, far movers, empty and clustered inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1608_01009_amd import pic
+from paper_1608_01009_amd import workloads as W
+
+from gpu_parity_util import KEYS, compare, log, one_step_parity, oracle_for, read_state
+
+pytestmark = pytest.mark.gpu
+
+
+def test_config1_full_size_steps_0_1_19_20_99():
+    wl = W.config1()
+    reps, sim = one_step_parity(wl, [0, 1, 19, 20, 99])
+    # push bit for bit: the same formula order on both sides
+    for k, rep in reps:
+        for key, v in rep.items():
+            if key.endswith(".exact"):
+                assert v == 1.0, (k, key, v)
+    sim.close()
+
+
+def test_thermal_noise_recipe_at_16cubed():
+    # the 64^3 / 50 ppc / v_th 0.05 / 1e-3 noise recipe on a 16^3 grid
+    wl = W.scaled(2, (16, 16, 16), 50, seed=21)
+    reps, sim = one_step_parity(wl, [0, 5, 19, 20])
+    sim.close()
+
+
+def test_two_species_and_ragged_counts():
+    base = W.scaled(2, (8, 8, 16), 7, seed=22)
+    ions = W.scaled(2, (8, 8, 16), 3, seed=23)
+    sp_i = ions.species[0]
+    sp_i.charge, sp_i.mass = 1.0, 1836.0
+    sp_i.ux *= 0.02
+    sp_i.uy *= 0.02
+    sp_i.uz *= 0.02
+    # drop a ragged number of particles from both
+    for sp, keep in ((base.species[0], 7 * 1024 - 13), (sp_i, 3 * 1024 - 101)):
+        for k in ("x", "y", "z", "ux", "uy", "uz"):
+            setattr(sp, k, np.ascontiguousarray(getattr(sp, k)[:keep]))
+    base.species.append(sp_i)
+    one_step_parity(base, [0, 3, 19])[1].close()
+
+
+@pytest.mark.parametrize("n,S,h", [((4, 4, 4), 4, 1), ((4, 8, 12), 4, 1), ((8, 8, 8), 2, 2),
+                                   ((6, 6, 6), 1, 1), ((12, 6, 6), 6, 1), ((10, 5, 5), 5, 1),
+                                   ((16, 8, 8), 4, 2)])
+def test_supercell_and_halo_shapes(n, S, h):
+    wl = W.plasma(f"shape-{n}-S{S}-h{h}", n, 9, 0.05, seed=30 + S, noise=1e-3, S=S, R=7)
+    one_step_parity(wl, [0, 6, 7], sim_kwargs=dict(halo=h))[1].close()
+
+
+def test_anisotropic_cells():
+    dx = (1.0, 0.5, 2.0)
+    wl = W.plasma("aniso", (8, 16, 4), 6, 0.05, seed=40, noise=1e-3, dx=dx,
+                  dt=W.courant_dt(dx, 0.9))
+    one_step_parity(wl, [0, 1, 4])[1].close()
+
+
+def test_far_movers_take_the_global_path():
+    # a relativistic beam drifts more than the halo before the next re-sort
+    wl = W.plasma("beam", (16, 16, 16), 2, 0.0, seed=50, noise=1e-2, R=40)
+    sp = wl.species[0]
+    rng = np.random.default_rng(51)
+    sp.ux[:] = 4.0 + rng.random(sp.n)
+    sp.uy[:] = -3.0
+    sp.uz[:] = 2.0 * rng.standard_normal(sp.n)
+    seen = {}
+
+    def check(sim, k, rep):
+        seen[k] = int(sim.counters()[0])
+
+    reps, sim = one_step_parity(wl, [0, 3, 8, 15, 30], extra_check=check)
+    assert seen[30] > 0, seen       # the far-mover path was exercised
+    sim.close()
+
+
+def test_empty_species_and_clustered_supercells():
+    n = (8, 8, 8)
+    rng = np.random.default_rng(60)
+    # all particles inside two supercells, the others empty
+    N = 1500
+    x = rng.random(N) * 4.0
+    y = rng.random(N) * 4.0
+    z = 4.0 + rng.random(N) * 4.0
+    x[::2] += 4.0
+    u = rng.normal(0, 0.1, (N, 3))
+    fields = [rng.uniform(-1e-2, 1e-2, 512) for _ in range(6)]
+    wl = W.Workload("clustered", n, (1.0, 1.0, 1.0), W.courant_dt(), 4, 20, 10,
+                    [W.Species(-1.0, 1.0, 0.05, x, y, z, u[:, 0].copy(), u[:, 1].copy(),
+                               u[:, 2].copy()),
+                     W.Species(1.0, 1836.0, 0.05, np.zeros(0), np.zeros(0), np.zeros(0),
+                               np.zeros(0), np.zeros(0), np.zeros(0))],
+                    fields)
+    one_step_parity(wl, [0, 2])[1].close()
+
+
+def test_fields_only_vacuum_step():
+    n = (8, 6, 10)
+    rng = np.random.default_rng(61)
+    fields = [rng.standard_normal(480) for _ in range(6)]
+    z0 = np.zeros(0)
+    wl = W.Workload("vacuum", n, (1.0, 1.0, 1.0), W.courant_dt(), 2, 20, 5,
+                    [W.Species(-1.0, 1.0, 0.1, z0, z0, z0, z0, z0, z0)], fields)
+    one_step_parity(wl, [0, 1, 3])[1].close()
