@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this size (a kernel of "
+                         "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PIC step here is built and timed on a "
@@ -112,7 +115,7 @@ def main():
     counters = sim.counters()
     value = n * args.steps / wall
     push_ms_avg = tm[0] / max(tm[4], 1)
-    bytes_launch = algorithmic_bytes_per_launch(n, wl.ncell)
+    bytes_launch = algorithmic_bytes_per_launch(n, wl.ncells)
     achieved = bytes_launch / (push_ms_avg * 1e-3) / 1e9
     traffic = measured_traffic()
     log(f"wall {wall*1e3:.2f} ms for {args.steps} steps; events: push+deposit {tm[0]:.2f} ms "
@@ -147,6 +150,14 @@ def main():
                      "avg_launch_us": push_ms_avg * 1e3},
         "cpu_baseline": None,
     }
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nel * 8} bytes read and written")
+        del a, b
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle steps")
         rec["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

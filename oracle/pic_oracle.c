@@ -289,9 +289,14 @@ void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
 }
 
 /* ---------------------------------------------------------------------------
- * Per-cell particle storage grouped by supercells (Sections 3 and 4.3): the
- * key orders particles by supercell (x-fastest over supercells), then by cell
- * inside the supercell (x-fastest).  The rebin is a stable sort on that key.
+ * Per-cell particle storage grouped by supercells (Sections 3 and 4.3).
+ *
+ * The key orders particles by supercell (x-fastest over supercells), then by
+ * cell inside the supercell (x-fastest).  A stable sort on that key groups
+ * every cell's particles, in their previous order.  Inside each supercell the
+ * cells' lists are then stored interleaved in rounds: round r holds, in
+ * increasing cell order, the r-th particle of every cell of the supercell
+ * that has more than r particles.
  * ------------------------------------------------------------------------- */
 int64_t orc_sort_key(const orc_grid* g, const double x[3]) {
     const int64_t S = g->S;
@@ -312,18 +317,38 @@ void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
                double* ux, double* uy, double* uz, int64_t* id) {
     if (n <= 0) return;
     const int64_t nkeys = g->n[0] * g->n[1] * g->n[2];
+    const int64_t S3 = g->S * g->S * g->S;
+    const int64_t nsc = nkeys / S3;
     int64_t* key = (int64_t*)malloc((size_t)n * sizeof(int64_t));
-    int64_t* cnt = (int64_t*)calloc((size_t)nkeys + 1, sizeof(int64_t));
+    int64_t* cnt = (int64_t*)calloc((size_t)nkeys, sizeof(int64_t));
+    int64_t* start = (int64_t*)malloc(((size_t)nkeys + 1) * sizeof(int64_t));
+    int64_t* fill = (int64_t*)malloc((size_t)nkeys * sizeof(int64_t));
+    int64_t* sorted = (int64_t*)malloc((size_t)n * sizeof(int64_t));
     int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
     double* tmp = (double*)malloc((size_t)n * sizeof(double));
     int64_t* itmp = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    /* stable counting sort by key: every cell's particles in previous order */
     for (int64_t p = 0; p < n; ++p) {
         double xp[3] = {x[p], y[p], z[p]};
         key[p] = orc_sort_key(g, xp);
-        cnt[key[p] + 1] += 1;
+        cnt[key[p]] += 1;
     }
-    for (int64_t k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k]; /* start offsets */
-    for (int64_t p = 0; p < n; ++p) perm[cnt[key[p]]++] = p; /* input order kept */
+    start[0] = 0;
+    for (int64_t k = 0; k < nkeys; ++k) start[k + 1] = start[k] + cnt[k];
+    for (int64_t k = 0; k < nkeys; ++k) fill[k] = start[k];
+    for (int64_t p = 0; p < n; ++p) sorted[fill[key[p]]++] = p;
+    /* interleave the cells of each supercell in rounds */
+    int64_t pos = 0;
+    for (int64_t sc = 0; sc < nsc; ++sc) {
+        int64_t maxc = 0;
+        for (int64_t l = 0; l < S3; ++l)
+            if (cnt[sc * S3 + l] > maxc) maxc = cnt[sc * S3 + l];
+        for (int64_t r = 0; r < maxc; ++r)
+            for (int64_t l = 0; l < S3; ++l) {
+                const int64_t k = sc * S3 + l;
+                if (cnt[k] > r) perm[pos++] = sorted[start[k] + r];
+            }
+    }
     permute_d(x, perm, n, tmp);
     permute_d(y, perm, n, tmp);
     permute_d(z, perm, n, tmp);
@@ -332,7 +357,7 @@ void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
     permute_d(uz, perm, n, tmp);
     for (int64_t i = 0; i < n; ++i) itmp[i] = id[perm[i]];
     memcpy(id, itmp, (size_t)n * sizeof(int64_t));
-    free(key); free(cnt); free(perm); free(tmp); free(itmp);
+    free(key); free(cnt); free(start); free(fill); free(sorted); free(perm); free(tmp); free(itmp);
 }
 
 /* One species' particle loop for one step, in array order (Section 2: field

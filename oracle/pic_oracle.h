@@ -62,7 +62,9 @@ void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
 /* Sort key (supercell-major, then local cell) of one in-domain position. */
 int64_t orc_sort_key(const orc_grid* g, const double x[3]);
 
-/* Stable counting sort of n particles by orc_sort_key; permutes the six
+/* Re-sort of n particles: stable sort by orc_sort_key, then inside every
+ * supercell the cells' particles interleaved in rounds (round r: the r-th
+ * particle of each cell with more than r, in cell order).  Permutes the six
  * state arrays and id in place. */
 void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
                double* ux, double* uy, double* uz, int64_t* id);

@@ -262,14 +262,70 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// The twelve J contributions of one segment that stays inside one cell,
+// ordered (d, bp, br) with d the J component and (bp, br) the offsets along
+// its two transverse axes in increasing axis order.
+__device__ __forceinline__ void vb_single(const double x0[3], const double x1[3], const int c[3],
+                                          const double jc[3], double v[12]) {
+    double a[3], b[3], dl[3], m[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        a[d] = x0[d] - (double)c[d];
+        b[d] = x1[d] - (double)c[d];
+        dl[d] = b[d] - a[d];
+        m[d] = 0.5 * (a[d] + b[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+        const int p = e1 < e2 ? e1 : e2;
+        const int r = e1 < e2 ? e2 : e1;
+        const double cross = (dl[p] * dl[r]) * (1.0 / 12.0);
+        const double flux = jc[d] * dl[d];
+        const double wp0 = 1.0 - m[p], wr0 = 1.0 - m[r];
+        v[4 * d + 0] = flux * (wp0 * wr0 + cross);
+        v[4 * d + 1] = flux * (wp0 * m[r] - cross);
+        v[4 * d + 2] = flux * (m[p] * wr0 - cross);
+        v[4 * d + 3] = flux * (m[p] * m[r] + cross);
+    }
+}
+
+// Layout of the J tile in LDS: node (tx, ty, tz) of component d lives at
+// d * JC + tx + PY * ty + PZ * tz.  For S = 4 the pitches are padded so that
+// the 32 cells of a half wave (one round covers the 64 cells of the
+// supercell) fall on 32 distinct bank pairs for every one of the twelve
+// contributions, which keeps the FP64 LDS atomics free of bank conflicts.
+template <int S, int H>
+struct JLayout {
+    static constexpr int TJ = S + 2 * H + 3;
+    static constexpr int PY = (S == 4 && H == 1) ? 12 : TJ;
+    static constexpr int PZ = (S == 4 && H == 1) ? 112 : TJ * TJ;
+    static constexpr int JC = PZ * (TJ - 1) + PY * (TJ - 1) + TJ;  // doubles per component
+};
+
+// LDS offset (relative to the node of the cell) of contribution j of
+// vb_single: j = 4 d + 2 bp + br.
+template <int PY, int PZ, int JC>
+__device__ __forceinline__ constexpr int jt_off(int j) {
+    const int d = j >> 2, bp = (j >> 1) & 1, br = j & 1;
+    // d = 0: (p, r) = (y, z); d = 1: (x, z); d = 2: (x, y)
+    const int sp = (d == 0) ? PY : 1;
+    const int sr = (d == 2) ? PY : PZ;
+    return d * JC + bp * sp + br * sr;
+}
+
 template <int S, int H>
 __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
     constexpr int T = S + 2 * H + 2;   // E/B tile edge in nodes
     constexpr int T2 = T * T, T3 = T2 * T;
-    constexpr int TJ = S + 2 * H + 3;  // J tile edge in nodes
-    constexpr int TJ2 = TJ * TJ, TJ3 = TJ2 * TJ;
+    using JL = JLayout<S, H>;
+    constexpr int TJ = JL::TJ;         // J tile edge in nodes
+    constexpr int PY = JL::PY, PZ = JL::PZ, JC = JL::JC;
+    constexpr int kWaves = kBlock / 64;
+    constexpr int QCAP = 28;           // queued cell-crossing particles per wave
     __shared__ double eb[6 * T3];
-    __shared__ double jt[3 * TJ3];
+    __shared__ double jt[3 * JC];
+    __shared__ double qb[kWaves][6][QCAP];
 
     const int sc = xcd_block(blockIdx.x, gridDim.x);
     const int p0 = a.sc_off[sc], p1 = a.sc_off[sc + 1];
@@ -282,6 +338,9 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
     const int sy = syz % g.ns[1], sz = syz / g.ns[1];
     const int base[3] = {sx * S, sy * S, sz * S};          // first cell of the supercell
     const int org[3] = {base[0] - H - 1, base[1] - H - 1, base[2] - H - 1};  // tile origin
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (int t = threadIdx.x; t < 6 * T3; t += kBlock) {
         const int c = t / T3;
@@ -291,97 +350,197 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
                   gz = wrapi(org[2] + tz, nz);
         eb[t] = a.EB[c][gx + nx * (gy + ny * gz)];
     }
-    for (int t = threadIdx.x; t < 3 * TJ3; t += kBlock) jt[t] = 0.0;
+    for (int t = threadIdx.x; t < 3 * JC; t += kBlock) jt[t] = 0.0;
     __syncthreads();
 
     const double L[3] = {(double)nx, (double)ny, (double)nz};
     const int nn[3] = {nx, ny, nz};
 
-    for (int ip = p0 + (int)threadIdx.x; ip < p1; ip += kBlock) {
-        double x0[3] = {a.p.x[ip], a.p.y[ip], a.p.z[ip]};
-        double u[3] = {a.p.ux[ip], a.p.uy[ip], a.p.uz[ip]};
-        if (!(finite3(x0[0], x0[1], x0[2]) && finite3(u[0], u[1], u[2]))) {
-            atomicOr(a.err, ERR_NONFINITE);
-            continue;
-        }
-        double fl[3];
-        int c0[3], rel[3];
-        bool inside = true;
+    // relative cell of c0 inside the tile window [-H, S+H), periodic
+    auto relcell = [&](const int c0[3], int rel[3]) {
+        bool in = true;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            fl[d] = floor(x0[d]);
-            c0[d] = (int)fl[d];
             int r = c0[d] - base[d];
             if (r >= S + H)
                 r -= nn[d];
             else if (r < -H)
                 r += nn[d];
             rel[d] = r;
-            inside = inside && (r >= -H) && (r < S + H);
+            in = in && (r >= -H) && (r < S + H);
         }
-        Stencil st;
-        make_stencil(x0, fl, st);
-        double E[3], Bf[3];
-        // tile node index of cell c0 is rel + H + 1
-        int off[3];
-        if (inside) {
+        return in;
+    };
+    // deposit of a general move (any number of plane crossings) into the tile
+    auto deposit_tile = [&](const double x0[3], const double x1[3]) {
+        int c0[3], c1[3], rel[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) off[d] = rel[d] + H + 1 - c0[d];
-            gather6(st, off,
-                    [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
-                        return eb[comp * T3 + (ix + da) + T * (iy + db) + T2 * (iz + dc)];
-                    },
-                    E, Bf);
-        } else {
-            atomicAdd(a.nfar, 1ull);
-            off[0] = off[1] = off[2] = 0;
-            gather6(st, off,
-                    [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
-                        return a.EB[comp][wrapi(ix + da, nx) +
-                                          nx * (wrapi(iy + db, ny) + ny * wrapi(iz + dc, nz))];
-                    },
-                    E, Bf);
+        for (int d = 0; d < 3; ++d) {
+            c0[d] = (int)floor(x0[d]);
+            c1[d] = (int)floor(x1[d]);
         }
-        double x1[3];
-        boris_advance(a.sp, g, E, Bf, u, x0, x1);
-        if (!(finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]))) {
-            atomicOr(a.err, ERR_NONFINITE);
-            continue;
+        relcell(c0, rel);
+        const int jo0 = rel[0] + H + 1 - c0[0], jo1 = rel[1] + H + 1 - c0[1],
+                  jo2 = rel[2] + H + 1 - c0[2];
+        vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double v) {
+            atomicAdd(&jt[d * JC + (i + jo0) + PY * (j + jo1) + PZ * (k + jo2)], v);
+        });
+    };
+    // queued crossers of this wave: one per lane, then the queue is empty
+    auto drain = [&](int cnt) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < cnt) {
+            const double q0[3] = {qb[wv][0][lane], qb[wv][1][lane], qb[wv][2][lane]};
+            const double q1[3] = {qb[wv][3][lane], qb[wv][4][lane], qb[wv][5][lane]};
+            deposit_tile(q0, q1);
         }
-        int c1[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
-        if (inside) {
-            // J tile node of lattice node n is n - c0 + rel + H + 1 per axis
-            const int jo0 = rel[0] + H + 1 - c0[0], jo1 = rel[1] + H + 1 - c0[1],
-                      jo2 = rel[2] + H + 1 - c0[2];
-            vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double v) {
-                atomicAdd(&jt[d * TJ3 + (i + jo0) + TJ * (j + jo1) + TJ2 * (k + jo2)], v);
-            });
-        } else {
-            vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double v) {
-                unsafeAtomicAdd(
-                    &a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], v);
-            });
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+
+    int qcount = 0;  // wave-uniform
+    unsigned long long nfar = 0;
+    // software pipeline: the next particle's state is loaded one iteration ahead
+    double nxt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+        const int ip = p0 + (int)threadIdx.x;
+        if (ip < p1) {
+            nxt[0] = a.p.x[ip]; nxt[1] = a.p.y[ip]; nxt[2] = a.p.z[ip];
+            nxt[3] = a.p.ux[ip]; nxt[4] = a.p.uy[ip]; nxt[5] = a.p.uz[ip];
         }
-        // positions are stored wrapped into [0, n)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) x1[d] = wrap_coord(x1[d], L[d]);
-        a.p.x[ip] = x1[0];
-        a.p.y[ip] = x1[1];
-        a.p.z[ip] = x1[2];
-        a.p.ux[ip] = u[0];
-        a.p.uy[ip] = u[1];
-        a.p.uz[ip] = u[2];
     }
+    for (int pb = p0; pb < p1; pb += kBlock) {
+        const int ip = pb + (int)threadIdx.x;
+        const bool valid = ip < p1;
+        double x0[3] = {nxt[0], nxt[1], nxt[2]};
+        double u[3] = {nxt[3], nxt[4], nxt[5]};
+        {
+            const int in = ip + kBlock;
+            if (in < p1) {
+                nxt[0] = a.p.x[in]; nxt[1] = a.p.y[in]; nxt[2] = a.p.z[in];
+                nxt[3] = a.p.ux[in]; nxt[4] = a.p.uy[in]; nxt[5] = a.p.uz[in];
+            }
+        }
+        bool simple = false, crosser = false;
+        double x1[3] = {0.0, 0.0, 0.0};
+        double v[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) v[j] = 0.0;
+        int key = -1;
+        if (valid) {
+            bool ok = finite3(x0[0], x0[1], x0[2]) && finite3(u[0], u[1], u[2]);
+            double fl[3];
+            int c0[3], rel[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                fl[d] = ok ? floor(x0[d]) : 0.0;
+                c0[d] = (int)fl[d];
+            }
+            const bool inside = ok && relcell(c0, rel);
+            Stencil st;
+            make_stencil(x0, fl, st);
+            double E[3] = {0.0, 0.0, 0.0}, Bf[3] = {0.0, 0.0, 0.0};
+            int off[3];
+            if (inside) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) off[d] = rel[d] + H + 1 - c0[d];
+                gather6(st, off,
+                        [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
+                            return eb[comp * T3 + (ix + da) + T * (iy + db) + T2 * (iz + dc)];
+                        },
+                        E, Bf);
+            } else if (ok) {
+                off[0] = off[1] = off[2] = 0;
+                gather6(st, off,
+                        [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
+                            return a.EB[comp][wrapi(ix + da, nx) +
+                                              nx * (wrapi(iy + db, ny) + ny * wrapi(iz + dc, nz))];
+                        },
+                        E, Bf);
+            }
+            if (ok) {
+                boris_advance(a.sp, g, E, Bf, u, x0, x1);
+                ok = finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]);
+            }
+            if (!ok) {
+                atomicOr(a.err, ERR_NONFINITE);
+            } else {
+                int c1[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
+                if (inside) {
+                    if (c1[0] == c0[0] && c1[1] == c0[1] && c1[2] == c0[2]) {
+                        simple = true;
+                        vb_single(x0, x1, c0, a.sp.jc, v);
+                        key = (rel[0] + H + 1) + PY * (rel[1] + H + 1) + PZ * (rel[2] + H + 1);
+                    } else {
+                        crosser = true;
+                    }
+                } else {
+                    nfar += 1;
+                    vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double vv) {
+                        unsafeAtomicAdd(
+                            &a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], vv);
+                    });
+                }
+                // positions are stored wrapped into [0, n)
+                double xw[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) xw[d] = wrap_coord(x1[d], L[d]);
+                a.p.x[ip] = xw[0];
+                a.p.y[ip] = xw[1];
+                a.p.z[ip] = xw[2];
+                a.p.ux[ip] = u[0];
+                a.p.uy[ip] = u[1];
+                a.p.uz[ip] = u[2];
+            }
+        }
+
+        // Single-cell moves: twelve LDS atomic adds per lane.  Within a round
+        // of the stored order the lanes of a wave sit in distinct cells.
+        if (simple) {
+#pragma unroll
+            for (int j = 0; j < 12; ++j) atomicAdd(&jt[key + jt_off<PY, PZ, JC>(j)], v[j]);
+        }
+
+        // Cell-crossing moves: queued per wave, deposited one per lane.
+        {
+            const unsigned long long cm = __ballot(crosser);
+            const int nnew = __popcll(cm);
+            if (nnew > QCAP) {
+                if (crosser) deposit_tile(x0, x1);
+            } else if (nnew > 0) {
+                if (qcount + nnew > QCAP) {
+                    drain(qcount);
+                    qcount = 0;
+                }
+                if (crosser) {
+                    const int slot = qcount + __popcll(cm & lt_mask);
+                    qb[wv][0][slot] = x0[0];
+                    qb[wv][1][slot] = x0[1];
+                    qb[wv][2][slot] = x0[2];
+                    qb[wv][3][slot] = x1[0];
+                    qb[wv][4][slot] = x1[1];
+                    qb[wv][5][slot] = x1[2];
+                }
+                qcount += nnew;
+            }
+        }
+    }
+    if (qcount > 0) drain(qcount);
+    if (nfar) atomicAdd(a.nfar, nfar);
     __syncthreads();
 
+    constexpr int TJ2 = TJ * TJ, TJ3 = TJ2 * TJ;
     for (int t = threadIdx.x; t < 3 * TJ3; t += kBlock) {
-        const double v = jt[t];
+        const int c = t / TJ3;
+        const int r = t - c * TJ3;
+        const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
+        const double v = jt[c * JC + tx + PY * ty + PZ * tz];
         if (v != 0.0) {
-            const int c = t / TJ3;
-            const int r = t - c * TJ3;
-            const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
             const int gx = wrapi(org[0] + tx, nx), gy = wrapi(org[1] + ty, ny),
                       gz = wrapi(org[2] + tz, nz);
             unsafeAtomicAdd(&a.J[c][gx + nx * (gy + ny * gz)], v);
@@ -397,15 +556,15 @@ hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
 
 template <int S, int H>
 constexpr int lds_bytes_sh() {
-    return (6 * (S + 2 * H + 2) * (S + 2 * H + 2) * (S + 2 * H + 2) +
-            3 * (S + 2 * H + 3) * (S + 2 * H + 3) * (S + 2 * H + 3)) *
+    return (6 * (S + 2 * H + 2) * (S + 2 * H + 2) * (S + 2 * H + 2) + 3 * JLayout<S, H>::JC +
+            (kBlock / 64) * 6 * 28) *
            (int)sizeof(double);
 }
 
 }  // namespace
 
-// Supported (S, h) pairs: the two LDS tiles of one workgroup must fit in the
-// 64 KiB a workgroup may statically allocate.
+// Supported (S, h) pairs (the LDS tiles of one workgroup must fit in the
+// 160 KiB of a CU).
 #define PIC_SH_TABLE(X) \
     X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 1) X(4, 1) X(4, 2) X(5, 1) X(6, 1)
 

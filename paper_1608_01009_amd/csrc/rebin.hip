@@ -8,9 +8,12 @@
 //   scan    exclusive scan over hist in (digit, block) order
 //   scatter per block: stable rank of every element among equal digits
 //           (wave-level ballot match, waves in order), write to its slot.
-// Stability of each pass gives a stable sort overall; the permutation is then
-// applied to the SoA arrays and ids, and the supercell offsets are taken from
-// the sorted keys.
+// Stability of each pass gives a stable sort overall.  The supercell offsets
+// are taken from the sorted keys; then, inside every supercell, the cells'
+// particle lists are interleaved in rounds (round r holds the r-th particle of
+// every cell with more than r, in cell order), so that the 64 lanes of a wave
+// working through a round touch 64 different cells.  The final permutation is
+// applied to the SoA arrays and ids.
 #include "pic_internal.h"
 
 namespace pic {
@@ -219,6 +222,44 @@ __global__ void __launch_bounds__(kBlock) offsets_kernel(const unsigned* key, in
     }
 }
 
+// One workgroup per supercell: position of sorted element i in the round
+// order, pos = start + sum_l min(cnt_l, rank) + #{l < cell : cnt_l > rank}.
+constexpr int kMaxS3 = 512;
+
+__global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
+                                                            const unsigned* perm,
+                                                            const int* sc_off, int S3,
+                                                            unsigned* out) {
+    __shared__ int cnt[kMaxS3];
+    __shared__ int cst[kMaxS3];
+    const int sc = blockIdx.x;
+    const int s0 = sc_off[sc], s1 = sc_off[sc + 1];
+    if (s0 >= s1) return;
+    for (int l = threadIdx.x; l < S3; l += kBlock) cnt[l] = 0;
+    __syncthreads();
+    const unsigned kb = (unsigned)sc * (unsigned)S3;
+    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) atomicAdd(&cnt[key[i] - kb], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = s0;
+        for (int l = 0; l < S3; ++l) {
+            cst[l] = run;
+            run += cnt[l];
+        }
+    }
+    __syncthreads();
+    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
+        const int loc = (int)(key[i] - kb);
+        const int rank = i - cst[loc];
+        int pos = s0;
+        for (int l = 0; l < S3; ++l) {
+            const int c = cnt[l];
+            pos += (c < rank ? c : rank) + ((l < loc && c > rank) ? 1 : 0);
+        }
+        out[pos] = perm[i];
+    }
+}
+
 int nblk(int64_t n, int per) {
     int64_t b = (n + per - 1) / per;
     return b < 1 ? 1 : (int)b;
@@ -306,9 +347,12 @@ hipError_t launch_rebin(const Geom& g, int64_t n64, const Parts& src, const Part
         unsigned* t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
-    hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, vin, src, dst);
     hipLaunchKernelGGL(offsets_kernel, dim3(grid_for((int64_t)n + 1)), dim3(kBlock), 0, s, kin, n,
                        S3, g.nsc, sc_off);
+    if (S3 > kMaxS3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(interleave_kernel, dim3(g.nsc), dim3(kBlock), 0, s, kin, vin, sc_off, S3,
+                       kout);
+    hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, kout, src, dst);
     return hipGetLastError();
 }
 

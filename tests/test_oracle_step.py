@@ -13,8 +13,9 @@ Section 3: charge-conserving deposition; Section 4.3: supercell grouping).
   For k = 2 pi / 16 the alias-free value is 0.99380 and the bare leapfrog
   value 1.00351; the measured value matches the alias sum to 1e-5 for the
   three lowest modes.
-* Rebin: the stored order is the stable sort by (supercell, cell in
-  supercell), recomputed here with numpy.
+* Rebin: the stored order groups particles by supercell and interleaves the
+  cells of a supercell in rounds; recomputed here with numpy as a sort by
+  the composite key (supercell, rank in cell, cell).
 """
 import math
 
@@ -129,7 +130,7 @@ def test_cold_plasma_oscillation_frequency(orc, mode):
         assert abs(p[1] - _discrete_cold_omega(k, dt, other)) > 1e-3
 
 
-def test_rebin_is_stable_sort_by_supercell_key(orc):
+def test_rebin_order_supercell_rounds(orc):
     n, S = (8, 12, 4), 4
     rng = np.random.default_rng(9)
     N = 3000
@@ -144,7 +145,15 @@ def test_rebin_is_stable_sort_by_supercell_key(orc):
     ns = [n[d] // S for d in range(3)]
     key = ((c[:, 0] // S + ns[0] * (c[:, 1] // S + ns[1] * (c[:, 2] // S))) * S ** 3
            + (c[:, 0] % S + S * (c[:, 1] % S + S * (c[:, 2] % S))))
-    perm = np.argsort(key, kind="stable")
+    # independent formulation of the stored order: sort by the composite key
+    # (supercell, rank of the particle among its cell's particles in input
+    # order, cell in supercell)
+    S3 = S ** 3
+    order1 = np.argsort(key, kind="stable")
+    sk = key[order1]
+    rank = np.empty(N, dtype=np.int64)
+    rank[order1] = np.arange(N) - np.searchsorted(sk, sk, side="left")
+    perm = np.lexsort((key % S3, rank, key // S3))
     got = sim.particles(0)
     assert np.array_equal(got["id"], ids[perm])
     assert np.array_equal(got["x"], P[perm, 0]) and np.array_equal(got["uz"], u[perm, 2])
@@ -152,3 +161,28 @@ def test_rebin_is_stable_sort_by_supercell_key(orc):
     g = orc.make_grid(n, (1, 1, 1), 0.2, S)
     for p in range(0, N, 97):
         assert orc.sort_key(g, P[p]) == key[p]
+
+
+def test_rebin_order_clustered_and_rounds_structure(orc):
+    """Very uneven cell counts (one cell holds most particles): the rounds end
+    with the crowded cell's particles alone, in input order."""
+    n, S = (4, 4, 8), 4
+    rng = np.random.default_rng(10)
+    N = 400
+    P = np.empty((N, 3))
+    P[:300] = np.array([1.5, 2.5, 6.5]) + rng.uniform(-0.4, 0.4, (300, 3))
+    P[300:] = rng.random((100, 3)) * np.array(n)
+    ids = np.arange(N, dtype=np.int64)
+    z = np.zeros(N)
+    sim = orc.OracleSim(n, (1.0, 1.0, 1.0), 0.2, [(-1.0, 1.0, 0.1)], S=S, R=20)
+    sim.load_particles(0, P[:, 0], P[:, 1], P[:, 2], z, z, z, ids)
+    got = sim.particles(0)["id"]
+    # the crowded cell (1, 2, 6) -> supercell 1; its particles appear in input
+    # order, and the last ones form single-particle rounds at the very end
+    crowded = [i for i in got if i < 300]
+    assert crowded == sorted(crowded)
+    c = np.floor(P[got]).astype(int)
+    sc = (c[:, 2] // 4)
+    assert np.all(np.diff(sc) >= 0)
+    tail = got[-150:]
+    assert np.all(tail < 300)
