@@ -70,7 +70,8 @@ typedef struct {
     double charge;          /* q in elementary charges */
     double mass;            /* m in electron masses, > 0 */
     double weight;          /* w > 0: physical particles per macro-particle */
-    int64_t capacity;       /* maximum number of particles of this species, < 2^31 */
+    int64_t capacity;       /* maximum number of particles of this species, < 2^29
+                               (each SoA array stays below 4 GiB) */
 } pic_species_t;
 
 /* Create a context on the current HIP device.  dx[3] > 0 are the cell sizes,

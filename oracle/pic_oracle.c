@@ -43,9 +43,13 @@ static int64_t lin(const orc_grid* g, int64_t i, int64_t j, int64_t k) {
  * Section 3 form factor).  Each component is interpolated trilinearly from the
  * eight nearest points of its own staggered lattice:
  *   xi_d = x_d - s_d, i_d = floor(xi_d), f_d = xi_d - i_d,
- *   F_p = sum_{a,b,c in {0,1}} w_a(f_x) w_b(f_y) w_c(f_z) F[i+a, j+b, k+c],
- *   w_0(f) = 1 - f, w_1(f) = f; summed with a outermost, c innermost.
+ * as nested linear interpolation, first along x, then y, then z:
+ *   lerp(a, b, f) = a + f (b - a), evaluated as fma(f, b - a, a),
+ * which equals sum_{a,b,c} w_a(f_x) w_b(f_y) w_c(f_z) F[i+a, j+b, k+c] with
+ * w_0(f) = 1 - f, w_1(f) = f.
  * ------------------------------------------------------------------------- */
+static double lerp(double a, double b, double f) { return fma(f, b - a, a); }
+
 void orc_gather(const orc_grid* g, const double* const EB[6], const double xp[3],
                 double out[6]) {
     for (int c = 0; c < 6; ++c) {
@@ -57,19 +61,17 @@ void orc_gather(const orc_grid* g, const double* const EB[6], const double xp[3]
             i[d] = (int64_t)fl;
             f[d] = xi - fl;
         }
-        double acc = 0.0;
-        for (int a = 0; a < 2; ++a) {
-            double wa = a ? f[0] : 1.0 - f[0];
+        double fz[2];
+        for (int cc = 0; cc < 2; ++cc) {
+            double fy[2];
             for (int b = 0; b < 2; ++b) {
-                double wb = b ? f[1] : 1.0 - f[1];
-                for (int cc = 0; cc < 2; ++cc) {
-                    double wc = cc ? f[2] : 1.0 - f[2];
-                    double w = (wa * wb) * wc;
-                    acc = acc + w * EB[c][lin(g, i[0] + a, i[1] + b, i[2] + cc)];
-                }
+                double f0 = EB[c][lin(g, i[0], i[1] + b, i[2] + cc)];
+                double f1 = EB[c][lin(g, i[0] + 1, i[1] + b, i[2] + cc)];
+                fy[b] = lerp(f0, f1, f[0]);
             }
+            fz[cc] = lerp(fy[0], fy[1], f[1]);
         }
-        out[c] = acc;
+        out[c] = lerp(fz[0], fz[1], f[2]);
     }
 }
 

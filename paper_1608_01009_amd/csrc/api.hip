@@ -63,6 +63,9 @@ struct pic_ctx {
     size_t scratch_bytes = 0;
     unsigned* d_err = nullptr;
     unsigned long long* d_nfar = nullptr;
+    int* far_q = nullptr;          // far-mover queue (capacity of the largest species)
+    unsigned* far_n = nullptr;     // two queue counters, used alternately by launches
+    int far_phase = 0;
     unsigned* h_err = nullptr;
     double* rho = nullptr;
     double* tmp = nullptr;
@@ -254,8 +257,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         if (!std::isfinite(q.charge) || !(q.mass > 0.0) || !std::isfinite(q.mass) ||
             !(q.weight > 0.0) || !std::isfinite(q.weight))
             return bad("species charge must be finite, mass and weight finite and > 0");
-        if (q.capacity < 0 || q.capacity >= (int64_t(1) << 31))
-            return bad("species capacity must be in [0, 2^31)");
+        if (q.capacity < 0 || q.capacity >= (int64_t(1) << 29))
+            return bad("species capacity must be in [0, 2^29)");
     }
 
     pic_ctx* c = new (std::nothrow) pic_ctx();
@@ -307,7 +310,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         (e = dalloc(c, (void**)&c->d_acc, (2 + 64) * sizeof(double))) != hipSuccess ||
         (e = dalloc(c, (void**)&c->d_max, 2 * sizeof(unsigned long long))) != hipSuccess ||
         (e = dalloc(c, (void**)&c->d_err, 256)) != hipSuccess ||
-        (e = dalloc(c, (void**)&c->d_nfar, 256)) != hipSuccess)
+        (e = dalloc(c, (void**)&c->d_nfar, 256)) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->far_n, 256)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc"));
     if ((e = hipHostMalloc((void**)&c->h_err, 256, hipHostMallocDefault)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipHostMalloc"));
@@ -342,6 +346,9 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         if ((e = dalloc(c, (void**)&st.sc_off, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess)
             return cfail(hip_fail(c, e, "hipMalloc sc_off"));
     }
+    if ((e = dalloc(c, (void**)&c->far_q, (size_t)(maxcap > 0 ? maxcap : 1) * sizeof(int))) !=
+        hipSuccess)
+        return cfail(hip_fail(c, e, "hipMalloc far queue"));
     c->scratch_bytes = rebin_scratch_bytes(maxcap, g);
     if ((e = dalloc(c, &c->scratch, c->scratch_bytes)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc sort scratch"));
@@ -354,7 +361,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
             return cfail(hip_fail(c, e, "zero fields"));
     }
     if ((e = hipMemsetAsync(c->d_err, 0, 256, c->stream)) != hipSuccess ||
-        (e = hipMemsetAsync(c->d_nfar, 0, 256, c->stream)) != hipSuccess)
+        (e = hipMemsetAsync(c->d_nfar, 0, 256, c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->far_n, 0, 256, c->stream)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipMemsetAsync"));
     for (auto& st : c->sp) {
         // no particles yet: every supercell empty
@@ -461,7 +469,9 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
                 if (s.n == 0) continue;
                 Timed t(c, ST_PUSH);
                 HIPCHK(c, launch_push_deposit(c->g, s.c, s.buf[s.cur], s.sc_off, f, Jd, c->d_err,
-                                              c->d_nfar, c->stream));
+                                              c->d_nfar, c->far_q, c->far_n + c->far_phase,
+                                              c->far_n + (1 - c->far_phase), c->stream));
+                c->far_phase = 1 - c->far_phase;
                 if (c->timers) c->push_launches++;
             }
             {

@@ -54,11 +54,13 @@ struct Fields {
 
 // Gather + Boris + advance + VB deposit + wrap for every particle of one
 // species; deposits are accumulated into J (which must hold the sum of the
-// previous species of this step, or zero).  Returns the LDS bytes used per
-// workgroup through lds_bytes (may be NULL).
+// previous species of this step, or zero).  far_q (capacity >= particles)
+// and the counters far_n (zero on entry) / far_n_next (cleared here for the
+// next launch) carry the particles outside their tile to a second kernel.
 hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p,
                                const int* sc_off, const Fields& f, double* const J[3],
-                               unsigned* err, unsigned long long* nfar, hipStream_t s);
+                               unsigned* err, unsigned long long* nfar, int* far_q,
+                               unsigned* far_n, unsigned* far_n_next, hipStream_t s);
 int push_deposit_lds_bytes(const Geom& g);
 bool push_deposit_supported(int S, int h);
 

@@ -27,7 +27,9 @@
 namespace pic {
 namespace {
 
-constexpr int kBlock = 256;
+// 8 waves per workgroup; with two workgroups per CU (LDS) and at most 128
+// VGPRs this keeps 4 waves on every SIMD.
+constexpr int kBlock = 512;
 
 __device__ __forceinline__ int wrapi(int i, int n) {
     int r = i % n;
@@ -52,25 +54,29 @@ struct PDArgs {
     double* J[3];
     unsigned* err;
     unsigned long long* nfar;
+    int* far_q;          // indices of particles outside their supercell's tile
+    unsigned* far_n;     // queue length for this launch
+    unsigned* far_n_next;  // queue length of the next launch (cleared by far_kernel)
 };
 
-// Trilinear cloud-in-cell sum of one component in the order
-// sum_a sum_b sum_c ((w_a w_b) w_c) F[a, b, c]  (a: x, b: y, c: z).
+// Cloud-in-cell (trilinear) interpolation of one component as nested linear
+// interpolation, x first, then y, then z, with lerp(a, b, f) = fma(f, b - a, a);
+// ld(a, b, c) returns the lattice value at offset (a, b, c).
 template <class Load>
-__device__ __forceinline__ double cic8(const Load& ld, const double wx[2], const double wy[2],
-                                       const double wz[2]) {
+__device__ __forceinline__ double cic8(const Load& ld, double fx, double fy, double fz) {
 #pragma clang fp contract(off)
-    double acc = 0.0;
+    double r[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) {
+        double q[2];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                double w = (wx[a] * wy[b]) * wz[c];
-                acc = acc + w * ld(a, b, c);
-            }
-    return acc;
+        for (int b = 0; b < 2; ++b) {
+            const double f0 = ld(0, b, c), f1 = ld(1, b, c);
+            q[b] = __fma_rn(fx, f1 - f0, f0);
+        }
+        r[c] = __fma_rn(fy, q[1] - q[0], q[0]);
+    }
+    return __fma_rn(fz, r[1] - r[0], r[0]);
 }
 
 // One straight segment A->B inside the cell with integer corner `cell`
@@ -96,7 +102,7 @@ __device__ __forceinline__ void vb_segment(const double A[3], const double B[3],
         const int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
         const int p = e1 < e2 ? e1 : e2;
         const int r = e1 < e2 ? e2 : e1;
-        const double cross = (dl[p] * dl[r]) / 12.0;
+        const double cross = (dl[p] * dl[r]) * (1.0 / 12.0);
         const double flux = jc[d] * dl[d];
 #pragma unroll
         for (int bp = 0; bp < 2; ++bp) {
@@ -111,6 +117,7 @@ __device__ __forceinline__ void vb_segment(const double A[3], const double B[3],
                 sink(d, cell[0] + o[0], cell[1] + o[1], cell[2] + o[2], flux * W);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -128,6 +135,8 @@ __device__ __forceinline__ void cswap(double& ta, int& da, double& tb, int& db) 
 // Split x0 -> x1 at the cell planes it crosses, in order of crossing time
 // (ties: x, y, z), and deposit every segment.  Each junction point is
 // x0 + t (x1 - x0) with its crossing coordinate set to the plane exactly.
+// The segment loop is kept rolled (the pending crossings rotate through three
+// registers) so that this rare path needs few registers.
 template <class Sink>
 __device__ __forceinline__ void vb_move(const double x0[3], const double x1[3], const int c0[3],
                                         const int c1[3], const double jc[3], const Sink& sink) {
@@ -142,31 +151,30 @@ __device__ __forceinline__ void vb_move(const double x0[3], const double x1[3], 
         t[d] = (c1[d] != c0[d]) ? (pl[d] - x0[d]) / dv[d] : __builtin_huge_val();
         dm[d] = d;
     }
-    const int nc = (c1[0] != c0[0]) + (c1[1] != c0[1]) + (c1[2] != c0[2]);
+    int left = (c1[0] != c0[0]) + (c1[1] != c0[1]) + (c1[2] != c0[2]);
     cswap(t[0], dm[0], t[1], dm[1]);
     cswap(t[1], dm[1], t[2], dm[2]);
     cswap(t[0], dm[0], t[1], dm[1]);
     double A[3] = {x0[0], x0[1], x0[2]};
     int cell[3] = {c0[0], c0[1], c0[2]};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (k > nc) break;
+#pragma unroll 1
+    for (;;) {
         double B[3];
-        if (k < nc) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) B[d] = (dm[k] == d) ? pl[d] : x0[d] + t[k] * dv[d];
-        } else {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) B[d] = x1[d];
-        }
+        for (int d = 0; d < 3; ++d)
+            B[d] = (left == 0) ? x1[d] : ((dm[0] == d) ? pl[d] : x0[d] + t[0] * dv[d]);
         vb_segment(A, B, cell, jc, sink);
-        if (k < nc) {
+        if (left == 0) break;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                A[d] = B[d];
-                if (dm[k] == d) cell[d] = c1[d];
-            }
+        for (int d = 0; d < 3; ++d) {
+            A[d] = B[d];
+            if (dm[0] == d) cell[d] = c1[d];
         }
+        t[0] = t[1];
+        dm[0] = dm[1];
+        t[1] = t[2];
+        dm[1] = dm[2];
+        --left;
     }
 }
 
@@ -212,26 +220,22 @@ __device__ __forceinline__ double wrap_coord(double v, double L) {
 }
 
 // Interpolation stencil of one position: for stagger 0 and 1/2 per axis the
-// lower lattice index and the two weights (1 - f, f).
+// lower lattice index and the fractional offset.
 struct Stencil {
     int i0[3], ih[3];
-    double w0[3][2], wh[3][2];
+    double f0[3], fh[3];
 };
 
 __device__ __forceinline__ void make_stencil(const double x[3], const double fl[3], Stencil& st) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double f0 = x[d] - fl[d];
         st.i0[d] = (int)fl[d];
-        st.w0[d][0] = 1.0 - f0;
-        st.w0[d][1] = f0;
+        st.f0[d] = x[d] - fl[d];
         const double xh = x[d] - 0.5;
         const double flh = floor(xh);
-        const double fh = xh - flh;
         st.ih[d] = (int)flh;
-        st.wh[d][0] = 1.0 - fh;
-        st.wh[d][1] = fh;
+        st.fh[d] = xh - flh;
     }
 }
 
@@ -245,17 +249,17 @@ __device__ __forceinline__ void gather6(const Stencil& st, const int off[3], con
     const int ix0 = st.i0[0] + off[0], iy0 = st.i0[1] + off[1], iz0 = st.i0[2] + off[2];
     const int ixh = st.ih[0] + off[0], iyh = st.ih[1] + off[1], izh = st.ih[2] + off[2];
     E[0] = cic8([&](int a, int b, int c) { return ld(0, ixh, iy0, iz0, a, b, c); },
-                st.wh[0], st.w0[1], st.w0[2]);
+                st.fh[0], st.f0[1], st.f0[2]);
     E[1] = cic8([&](int a, int b, int c) { return ld(1, ix0, iyh, iz0, a, b, c); },
-                st.w0[0], st.wh[1], st.w0[2]);
+                st.f0[0], st.fh[1], st.f0[2]);
     E[2] = cic8([&](int a, int b, int c) { return ld(2, ix0, iy0, izh, a, b, c); },
-                st.w0[0], st.w0[1], st.wh[2]);
+                st.f0[0], st.f0[1], st.fh[2]);
     Bf[0] = cic8([&](int a, int b, int c) { return ld(3, ix0, iyh, izh, a, b, c); },
-                 st.w0[0], st.wh[1], st.wh[2]);
+                 st.f0[0], st.fh[1], st.fh[2]);
     Bf[1] = cic8([&](int a, int b, int c) { return ld(4, ixh, iy0, izh, a, b, c); },
-                 st.wh[0], st.w0[1], st.wh[2]);
+                 st.fh[0], st.f0[1], st.fh[2]);
     Bf[2] = cic8([&](int a, int b, int c) { return ld(5, ixh, iyh, iz0, a, b, c); },
-                 st.wh[0], st.wh[1], st.w0[2]);
+                 st.fh[0], st.fh[1], st.f0[2]);
 }
 
 __device__ __forceinline__ bool finite3(double a, double b, double c) {
@@ -264,9 +268,11 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
 
 // The twelve J contributions of one segment that stays inside one cell,
 // ordered (d, bp, br) with d the J component and (bp, br) the offsets along
-// its two transverse axes in increasing axis order.
+// its two transverse axes in increasing axis order; add(j, v) receives them
+// one component at a time.
+template <class Add>
 __device__ __forceinline__ void vb_single(const double x0[3], const double x1[3], const int c[3],
-                                          const double jc[3], double v[12]) {
+                                          const double jc[3], const Add& add) {
     double a[3], b[3], dl[3], m[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -283,10 +289,11 @@ __device__ __forceinline__ void vb_single(const double x0[3], const double x1[3]
         const double cross = (dl[p] * dl[r]) * (1.0 / 12.0);
         const double flux = jc[d] * dl[d];
         const double wp0 = 1.0 - m[p], wr0 = 1.0 - m[r];
-        v[4 * d + 0] = flux * (wp0 * wr0 + cross);
-        v[4 * d + 1] = flux * (wp0 * m[r] - cross);
-        v[4 * d + 2] = flux * (m[p] * wr0 - cross);
-        v[4 * d + 3] = flux * (m[p] * m[r] + cross);
+        add(4 * d + 0, flux * (wp0 * wr0 + cross));
+        add(4 * d + 1, flux * (wp0 * m[r] - cross));
+        add(4 * d + 2, flux * (m[p] * wr0 - cross));
+        add(4 * d + 3, flux * (m[p] * m[r] + cross));
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -315,7 +322,8 @@ __device__ __forceinline__ constexpr int jt_off(int j) {
 }
 
 template <int S, int H>
-__global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+push_deposit_kernel(const PDArgs a) {
     constexpr int T = S + 2 * H + 2;   // E/B tile edge in nodes
     constexpr int T2 = T * T, T3 = T2 * T;
     using JL = JLayout<S, H>;
@@ -402,15 +410,23 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
     };
 
     int qcount = 0;  // wave-uniform
-    unsigned long long nfar = 0;
     // software pipeline: the next particle's state is loaded one iteration ahead
     double nxt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // Particle arrays are addressed with 32-bit byte offsets from the scalar
+    // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
+    // six loads and six stores of a particle share one offset register.
+    auto ld6 = [&](int ip, double o[6]) {
+        const unsigned b = (unsigned)ip * 8u;
+        o[0] = *(const double*)((const char*)a.p.x + b);
+        o[1] = *(const double*)((const char*)a.p.y + b);
+        o[2] = *(const double*)((const char*)a.p.z + b);
+        o[3] = *(const double*)((const char*)a.p.ux + b);
+        o[4] = *(const double*)((const char*)a.p.uy + b);
+        o[5] = *(const double*)((const char*)a.p.uz + b);
+    };
     {
         const int ip = p0 + (int)threadIdx.x;
-        if (ip < p1) {
-            nxt[0] = a.p.x[ip]; nxt[1] = a.p.y[ip]; nxt[2] = a.p.z[ip];
-            nxt[3] = a.p.ux[ip]; nxt[4] = a.p.uy[ip]; nxt[5] = a.p.uz[ip];
-        }
+        if (ip < p1) ld6(ip, nxt);
     }
     for (int pb = p0; pb < p1; pb += kBlock) {
         const int ip = pb + (int)threadIdx.x;
@@ -419,17 +435,10 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
         double u[3] = {nxt[3], nxt[4], nxt[5]};
         {
             const int in = ip + kBlock;
-            if (in < p1) {
-                nxt[0] = a.p.x[in]; nxt[1] = a.p.y[in]; nxt[2] = a.p.z[in];
-                nxt[3] = a.p.ux[in]; nxt[4] = a.p.uy[in]; nxt[5] = a.p.uz[in];
-            }
+            if (in < p1) ld6(in, nxt);
         }
-        bool simple = false, crosser = false;
+        bool crosser = false, far = false;
         double x1[3] = {0.0, 0.0, 0.0};
-        double v[12];
-#pragma unroll
-        for (int j = 0; j < 12; ++j) v[j] = 0.0;
-        int key = -1;
         if (valid) {
             bool ok = finite3(x0[0], x0[1], x0[2]) && finite3(u[0], u[1], u[2]);
             double fl[3];
@@ -440,11 +449,12 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
                 c0[d] = (int)fl[d];
             }
             const bool inside = ok && relcell(c0, rel);
-            Stencil st;
-            make_stencil(x0, fl, st);
-            double E[3] = {0.0, 0.0, 0.0}, Bf[3] = {0.0, 0.0, 0.0};
-            int off[3];
+            far = ok && !inside;
             if (inside) {
+                Stencil st;
+                make_stencil(x0, fl, st);
+                double E[3], Bf[3];
+                int off[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) off[d] = rel[d] + H + 1 - c0[d];
                 gather6(st, off,
@@ -452,58 +462,53 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
                             return eb[comp * T3 + (ix + da) + T * (iy + db) + T2 * (iz + dc)];
                         },
                         E, Bf);
-            } else if (ok) {
-                off[0] = off[1] = off[2] = 0;
-                gather6(st, off,
-                        [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
-                            return a.EB[comp][wrapi(ix + da, nx) +
-                                              nx * (wrapi(iy + db, ny) + ny * wrapi(iz + dc, nz))];
-                        },
-                        E, Bf);
-            }
-            if (ok) {
                 boris_advance(a.sp, g, E, Bf, u, x0, x1);
                 ok = finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]);
             }
             if (!ok) {
                 atomicOr(a.err, ERR_NONFINITE);
-            } else {
+            } else if (inside) {
                 int c1[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
-                if (inside) {
-                    if (c1[0] == c0[0] && c1[1] == c0[1] && c1[2] == c0[2]) {
-                        simple = true;
-                        vb_single(x0, x1, c0, a.sp.jc, v);
-                        key = (rel[0] + H + 1) + PY * (rel[1] + H + 1) + PZ * (rel[2] + H + 1);
-                    } else {
-                        crosser = true;
-                    }
-                } else {
-                    nfar += 1;
-                    vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double vv) {
-                        unsafeAtomicAdd(
-                            &a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], vv);
+                if (c1[0] == c0[0] && c1[1] == c0[1] && c1[2] == c0[2]) {
+                    // single-cell move: twelve LDS atomic adds; within a round
+                    // of the stored order the lanes of a wave sit in distinct
+                    // cells
+                    const int key =
+                        (rel[0] + H + 1) + PY * (rel[1] + H + 1) + PZ * (rel[2] + H + 1);
+                    vb_single(x0, x1, c0, a.sp.jc, [&](int j, double v) {
+                        atomicAdd(&jt[key + jt_off<PY, PZ, JC>(j)], v);
                     });
+                } else {
+                    crosser = true;
                 }
                 // positions are stored wrapped into [0, n)
                 double xw[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) xw[d] = wrap_coord(x1[d], L[d]);
-                a.p.x[ip] = xw[0];
-                a.p.y[ip] = xw[1];
-                a.p.z[ip] = xw[2];
-                a.p.ux[ip] = u[0];
-                a.p.uy[ip] = u[1];
-                a.p.uz[ip] = u[2];
+                const unsigned b = (unsigned)ip * 8u;
+                *(double*)((char*)a.p.x + b) = xw[0];
+                *(double*)((char*)a.p.y + b) = xw[1];
+                *(double*)((char*)a.p.z + b) = xw[2];
+                *(double*)((char*)a.p.ux + b) = u[0];
+                *(double*)((char*)a.p.uy + b) = u[1];
+                *(double*)((char*)a.p.uz + b) = u[2];
             }
         }
 
-        // Single-cell moves: twelve LDS atomic adds per lane.  Within a round
-        // of the stored order the lanes of a wave sit in distinct cells.
-        if (simple) {
-#pragma unroll
-            for (int j = 0; j < 12; ++j) atomicAdd(&jt[key + jt_off<PY, PZ, JC>(j)], v[j]);
+        // Far movers (outside the tile window) are left untouched here and
+        // queued for far_kernel, which gathers and deposits through global
+        // memory.
+        {
+            const unsigned long long fm = __ballot(far);
+            if (fm) {
+                const int lead = __ffsll((long long)fm) - 1;
+                unsigned base = 0;
+                if (lane == lead) base = atomicAdd(a.far_n, (unsigned)__popcll(fm));
+                base = (unsigned)__builtin_amdgcn_readlane((int)base, lead);
+                if (far) a.far_q[base + (unsigned)__popcll(fm & lt_mask)] = ip;
+            }
         }
 
         // Cell-crossing moves: queued per wave, deposited one per lane.
@@ -531,7 +536,6 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
         }
     }
     if (qcount > 0) drain(qcount);
-    if (nfar) atomicAdd(a.nfar, nfar);
     __syncthreads();
 
     constexpr int TJ2 = TJ * TJ, TJ3 = TJ2 * TJ;
@@ -548,9 +552,62 @@ __global__ void __launch_bounds__(kBlock) push_deposit_kernel(const PDArgs a) {
     }
 }
 
+// Particles that drifted beyond the halo of their supercell's tile since the
+// last re-sort: gather from the global E/B arrays, push, deposit with global
+// FP64 atomics, wrap and store.  The queue was filled by push_deposit_kernel.
+__global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
+    const unsigned n = *a.far_n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.far_n_next = 0u;
+    const Geom& g = a.g;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const double L[3] = {(double)nx, (double)ny, (double)nz};
+    unsigned long long cnt = 0;
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int ip = a.far_q[i];
+        double x0[3] = {a.p.x[ip], a.p.y[ip], a.p.z[ip]};
+        double u[3] = {a.p.ux[ip], a.p.uy[ip], a.p.uz[ip]};
+        double fl[3];
+        int c0[3], c1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            fl[d] = floor(x0[d]);
+            c0[d] = (int)fl[d];
+        }
+        Stencil st;
+        make_stencil(x0, fl, st);
+        double E[3], Bf[3], x1[3];
+        const int off[3] = {0, 0, 0};
+        gather6(st, off,
+                [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
+                    return a.EB[comp][wrapi(ix + da, nx) +
+                                      nx * (wrapi(iy + db, ny) + ny * wrapi(iz + dc, nz))];
+                },
+                E, Bf);
+        boris_advance(a.sp, g, E, Bf, u, x0, x1);
+        if (!(finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]))) {
+            atomicOr(a.err, ERR_NONFINITE);
+            continue;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
+        vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double vv) {
+            unsafeAtomicAdd(&a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], vv);
+        });
+        a.p.x[ip] = wrap_coord(x1[0], L[0]);
+        a.p.y[ip] = wrap_coord(x1[1], L[1]);
+        a.p.z[ip] = wrap_coord(x1[2], L[2]);
+        a.p.ux[ip] = u[0];
+        a.p.uy[ip] = u[1];
+        a.p.uz[ip] = u[2];
+        cnt += 1;
+    }
+    if (cnt) atomicAdd(a.nfar, cnt);
+}
+
 template <int S, int H>
 hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
     hipLaunchKernelGGL((push_deposit_kernel<S, H>), dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
 
@@ -584,7 +641,8 @@ int push_deposit_lds_bytes(const Geom& g) {
 
 hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p,
                                const int* sc_off, const Fields& f, double* const J[3],
-                               unsigned* err, unsigned long long* nfar, hipStream_t s) {
+                               unsigned* err, unsigned long long* nfar, int* far_q,
+                               unsigned* far_n, unsigned* far_n_next, hipStream_t s) {
     PDArgs args;
     args.g = g;
     args.sp = sp;
@@ -597,6 +655,9 @@ hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p
     }
     args.err = err;
     args.nfar = nfar;
+    args.far_q = far_q;
+    args.far_n = far_n;
+    args.far_n_next = far_n_next;
     if (g.nsc <= 0) return hipSuccess;
 #define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return launch_sh<s_, h_>(args, s);
     PIC_SH_TABLE(PIC_X)

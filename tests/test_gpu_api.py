@@ -144,8 +144,8 @@ def test_timers_and_counters():
     assert t[4] == 25 and t[5] == 25
     c = sim.counters()
     assert c[1] == 1 and c[2] == 25
-    # E/B tile 8^3 x 6, padded J tile 3 x 1001, crosser queues 4 x 6 x 28 doubles
-    assert c[3] == (6 * 512 + 3 * 1001 + 4 * 6 * 28) * 8
+    # E/B tile 8^3 x 6, padded J tile 3 x 1001, crosser queues 8 waves x 6 x 28 doubles
+    assert c[3] == (6 * 512 + 3 * 1001 + 8 * 6 * 28) * 8
     sim.close()
 
 
