@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle updates/s (gather+push+deposit) FP64 vs FP32-mixed; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "push_deposit_64c_50ppc_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "push_deposit_64c_50ppc_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_01009_amd", "csrc", "push_deposit.hip")
 
 
@@ -46,15 +46,20 @@ def algorithmic_bytes_per_launch(nparticles: int, ncell: int) -> int:
 
 def measured_traffic():
     """HBM bytes per push+deposit launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
+    if it was taken on the current kernel source; otherwise None."""
     if not os.path.exists(COUNTERS):
         return None
     try:
-        rec = json.load(open(COUNTERS))
+        fields = {}
+        for line in open(COUNTERS):
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
         src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if rec.get("kernel_source_sha256") != src_hash:
+        if fields.get("kernel_source_sha256") != src_hash:
             return None
-        return float(rec["hbm_bytes_per_launch"])
+        return float(fields["hbm_bytes_per_launch"])
     except Exception:
         return None
 

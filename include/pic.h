@@ -13,7 +13,9 @@
  *   4. Maxwell integration: Yee update B -= dt/2 curl E; E += dt (curl B - J);
  *      B -= dt/2 curl E (B kept at integer time levels).
  * Particles are kept grouped by supercells of S^3 cells (Section 4.3) and are
- * re-sorted (stable, by supercell then cell) every `rebin_every` steps.
+ * re-sorted every `rebin_every` steps: stably by supercell and cell, then inside
+ * each supercell the cells' lists are interleaved in rounds (round r holds the
+ * r-th particle of every cell with more than r, cells in x-fastest order).
  *
  * Units: c = eps0 = mu0 = 1.  Positions are in cell units, x_d in [0, n_d).
  * Momenta are u = gamma v / c.  charge q in elementary charges (electron
@@ -59,7 +61,8 @@ typedef enum {
 
 typedef struct {
     int32_t n[3];           /* cells per dimension; each a multiple of `supercell` */
-    int32_t supercell;      /* S: supercell edge in cells (Section 4.3); 1, 2, 4 or 8 */
+    int32_t supercell;      /* S: supercell edge in cells (Section 4.3); 1..6 with halo 1,
+                               1, 2 or 4 with halo 2 */
     int32_t rebin_every;    /* R >= 1: stable re-sort after every R-th step since the last sort */
     int32_t halo;           /* h: drift margin in cells of the per-supercell LDS tiles; 0 -> 1 */
     int32_t reserved[4];    /* must be zero */
@@ -83,8 +86,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
 
 /* Replace the particles of one species with n particles (n <= capacity).
  * x, y, z in [0, n_d) and finite u are required (PIC_EINVAL otherwise).
- * id may be NULL (ids 0..n-1).  The particles are stable-sorted by
- * (supercell, cell) and the re-sort counter restarts. */
+ * id may be NULL (ids 0..n-1).  The particles are re-sorted as described
+ * above (their input order breaks ties) and the re-sort counter restarts. */
 int pic_load_particles(pic_ctx* ctx, int32_t species, int64_t n,
                        const double* x, const double* y, const double* z,
                        const double* ux, const double* uy, const double* uz,
