@@ -27,8 +27,11 @@ struct SpeciesState {
     int64_t capacity = 0;
     int64_t n = 0;
     Parts buf[2] = {};
-    int cur = 0;
-    int* sc_off = nullptr;
+    int cur = 0;               // buffer holding the particles
+    int* sc_off = nullptr;     // supercell offsets of the (new) order
+    unsigned* keys = nullptr;  // sort keys written by the push before a re-sort
+    unsigned* perm = nullptr;  // re-sort order: new index -> index in buf[cur]
+    bool pending = false;      // buf[cur] is still in the old order; apply perm
     bool loaded = false;
 };
 
@@ -208,11 +211,21 @@ int compute_refs(pic_ctx* c) {
     return PIC_OK;
 }
 
-int do_rebin(pic_ctx* c, SpeciesState& s) {
-    const int src = s.cur, dst = 1 - s.cur;
-    HIPCHK(c, launch_rebin(c->g, s.n, s.buf[src], s.buf[dst], s.sc_off, c->scratch, c->d_err,
-                           c->stream));
-    s.cur = dst;
+// Order of the next re-sort from the keys written by the last push (or from
+// the positions when keys == nullptr); the data move with the next push.
+int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys) {
+    HIPCHK(c, launch_sort(c->g, s.n, keys, s.buf[s.cur], s.perm, s.sc_off, c->scratch, c->d_err,
+                          c->stream));
+    s.pending = true;
+    return PIC_OK;
+}
+
+// Apply a pending re-sort order to the particle data (outside pic_step).
+int resolve_pending(pic_ctx* c, SpeciesState& s) {
+    if (!s.pending) return PIC_OK;
+    HIPCHK(c, launch_permute(s.n, s.perm, s.buf[s.cur], s.buf[1 - s.cur], c->stream));
+    s.cur = 1 - s.cur;
+    s.pending = false;
     return PIC_OK;
 }
 
@@ -343,8 +356,10 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                 (e = dalloc(c, (void**)&P.id, (size_t)q.capacity * sizeof(int64_t))) != hipSuccess)
                 return cfail(hip_fail(c, e, "hipMalloc particles"));
         }
-        if ((e = dalloc(c, (void**)&st.sc_off, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess)
-            return cfail(hip_fail(c, e, "hipMalloc sc_off"));
+        if ((e = dalloc(c, (void**)&st.sc_off, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess ||
+            (e = dalloc(c, (void**)&st.keys, (size_t)q.capacity * sizeof(unsigned))) != hipSuccess ||
+            (e = dalloc(c, (void**)&st.perm, (size_t)q.capacity * sizeof(unsigned))) != hipSuccess)
+            return cfail(hip_fail(c, e, "hipMalloc sc_off / keys / perm"));
     }
     if ((e = dalloc(c, (void**)&c->far_q, (size_t)(maxcap > 0 ? maxcap : 1) * sizeof(int))) !=
         hipSuccess)
@@ -366,8 +381,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         return cfail(hip_fail(c, e, "hipMemsetAsync"));
     for (auto& st : c->sp) {
         // no particles yet: every supercell empty
-        if ((e = launch_rebin(g, 0, st.buf[0], st.buf[1], st.sc_off, c->scratch, c->d_err,
-                              c->stream)) != hipSuccess)
+        if ((e = launch_sort(g, 0, nullptr, st.buf[0], st.perm, st.sc_off, c->scratch, c->d_err,
+                             c->stream)) != hipSuccess)
             return cfail(hip_fail(c, e, "init offsets"));
     }
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess)
@@ -411,15 +426,19 @@ int pic_load_particles(pic_ctx* c, int32_t species, int64_t n, const double* x, 
     HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(unsigned), c->stream));
     s.n = n;
     s.cur = 0;
+    s.pending = false;
     {
         Timed t(c, ST_SORT);
-        int r = do_rebin(c, s);
+        int r = do_sort(c, s, nullptr);
+        if (r == PIC_OK) r = resolve_pending(c, s);
         if (r != PIC_OK) return r;
     }
     int r = sync_and_check(c, false);
     if (r != PIC_OK) {
         s.n = 0;
-        (void)launch_rebin(c->g, 0, s.buf[0], s.buf[1], s.sc_off, c->scratch, c->d_err, c->stream);
+        s.pending = false;
+        (void)launch_sort(c->g, 0, nullptr, s.buf[0], s.perm, s.sc_off, c->scratch, c->d_err,
+                          c->stream);
         (void)hipStreamSynchronize(c->stream);
         return r;
     }
@@ -465,13 +484,23 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
         Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
         for (int it = 0; it < n_steps; ++it) {
             double* const* Jd = c->J[c->jdep];
+            const bool sort_after = (c->steps_since_sort + 1 == c->R);
             for (auto& s : c->sp) {
                 if (s.n == 0) continue;
                 Timed t(c, ST_PUSH);
-                HIPCHK(c, launch_push_deposit(c->g, s.c, s.buf[s.cur], s.sc_off, f, Jd, c->d_err,
-                                              c->d_nfar, c->far_q, c->far_n + c->far_phase,
+                const Parts& src = s.buf[s.cur];
+                const Parts& dst = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
+                HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, s.pending ? s.perm : nullptr,
+                                              sort_after ? s.keys : nullptr, s.sc_off, f, Jd,
+                                              c->d_err, c->d_nfar, c->far_q,
+                                              c->far_n + c->far_phase,
                                               c->far_n + (1 - c->far_phase), c->stream));
                 c->far_phase = 1 - c->far_phase;
+                if (s.pending) {
+                    HIPCHK(c, launch_permute_ids(s.n, s.perm, src.id, dst.id, c->stream));
+                    s.cur = 1 - s.cur;
+                    s.pending = false;
+                }
                 if (c->timers) c->push_launches++;
             }
             {
@@ -482,15 +511,17 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
             c->jdep = 1 - c->jdep;
             c->steps++;
             if (c->timers) c->timed_steps++;
-            if (++c->steps_since_sort == c->R) {
+            if (sort_after) {
                 Timed t(c, ST_SORT);
                 for (auto& s : c->sp) {
                     if (s.n == 0) continue;
-                    int r = do_rebin(c, s);
+                    int r = do_sort(c, s, s.keys);
                     if (r != PIC_OK) return r;
                 }
                 c->steps_since_sort = 0;
                 c->rebins++;
+            } else {
+                c->steps_since_sort++;
             }
         }
     }
@@ -517,10 +548,14 @@ int pic_get_particles(pic_ctx* c, int32_t species, int64_t capacity, int64_t* n_
     c->err.clear();
     if (species < 0 || species >= (int)c->sp.size()) return fail(c, PIC_EINVAL, "bad species index");
     if (!n_out) return fail(c, PIC_EINVAL, "n_out must not be NULL");
-    const SpeciesState& s = c->sp[species];
+    SpeciesState& s = c->sp[species];
     *n_out = s.n;
     if (capacity < s.n) return fail(c, PIC_ECAPACITY, "caller capacity is smaller than n");
     HIPCHK(c, hipSetDevice(c->device));
+    {
+        int r = resolve_pending(c, s);
+        if (r != PIC_OK) return r;
+    }
     const Parts& P = s.buf[s.cur];
     const size_t b = (size_t)s.n * sizeof(double);
     double* dst[6] = {x, y, z, ux, uy, uz};

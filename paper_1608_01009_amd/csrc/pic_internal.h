@@ -54,10 +54,14 @@ struct Fields {
 
 // Gather + Boris + advance + VB deposit + wrap for every particle of one
 // species; deposits are accumulated into J (which must hold the sum of the
-// previous species of this step, or zero).  far_q (capacity >= particles)
+// previous species of this step, or zero).  Particle i of the new order is
+// read from src at perm[i] (or at i when perm is NULL) and written to dst at
+// i (dst may equal src when perm is NULL).  keys, when not NULL, receives the
+// sort key of every particle's new position.  far_q (capacity >= particles)
 // and the counters far_n (zero on entry) / far_n_next (cleared here for the
 // next launch) carry the particles outside their tile to a second kernel.
-hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p,
+hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& src,
+                               const Parts& dst, const unsigned* perm, unsigned* keys,
                                const int* sc_off, const Fields& f, double* const J[3],
                                unsigned* err, unsigned long long* nfar, int* far_q,
                                unsigned* far_n, unsigned* far_n_next, hipStream_t s);
@@ -71,11 +75,18 @@ hipError_t launch_fdtd(const Geom& g, const Fields& f, double* const J[3],
 // Fill n doubles with zero.
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 
-// Stable sort of one species by (supercell, cell): src -> dst, sc_off filled.
-// scratch must hold rebin_scratch_bytes(n, g) bytes.
+// Re-sort order of one species: perm (new index -> current index) and the
+// supercell offsets of the new order.  keys == NULL: computed from src's
+// positions, with ERR_BADPOS set for positions outside [0, n) or non-finite
+// values.  scratch must hold rebin_scratch_bytes(n, g) bytes.
 size_t rebin_scratch_bytes(int64_t n, const Geom& g);
-hipError_t launch_rebin(const Geom& g, int64_t n, const Parts& src, const Parts& dst,
-                        int* sc_off, void* scratch, unsigned* err, hipStream_t s);
+hipError_t launch_sort(const Geom& g, int64_t n, const unsigned* keys, const Parts& src,
+                       unsigned* perm, int* sc_off, void* scratch, unsigned* err, hipStream_t s);
+// dst[i] = src[perm[i]] for the six state arrays and the ids.
+hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, const Parts& dst,
+                          hipStream_t s);
+hipError_t launch_permute_ids(int64_t n, const unsigned* perm, const int64_t* src, int64_t* dst,
+                              hipStream_t s);
 
 // Diagnostics.
 hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, hipStream_t s);

@@ -48,7 +48,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 struct PDArgs {
     Geom g;
     SpeciesC sp;
-    Parts p;
+    Parts src;              // read: particle i of the new order at perm[i] (or i)
+    Parts dst;              // written: particle i at i
+    const unsigned* perm;   // nullptr: identity
+    unsigned* keys;         // nullptr: no sort keys wanted
     const int* sc_off;
     const double* EB[6];
     double* J[3];
@@ -119,6 +122,18 @@ __device__ __forceinline__ void vb_segment(const double A[3], const double B[3],
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// Sort key of a stored (wrapped) position: supercell * S^3 + cell in
+// supercell, both x-fastest.
+__device__ __forceinline__ unsigned sort_key(const Geom& g, const double x[3]) {
+    const int S = g.S;
+    int c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = (int)floor(x[d]);
+    const int sc = c[0] / S + g.ns[0] * (c[1] / S + g.ns[1] * (c[2] / S));
+    const int loc = c[0] % S + S * (c[1] % S + S * (c[2] % S));
+    return (unsigned)(sc * S * S * S + loc);
 }
 
 // Compare-exchange of (time, dimension) pairs ordered by time, then dimension.
@@ -416,13 +431,14 @@ push_deposit_kernel(const PDArgs a) {
     // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
     // six loads and six stores of a particle share one offset register.
     auto ld6 = [&](int ip, double o[6]) {
-        const unsigned b = (unsigned)ip * 8u;
-        o[0] = *(const double*)((const char*)a.p.x + b);
-        o[1] = *(const double*)((const char*)a.p.y + b);
-        o[2] = *(const double*)((const char*)a.p.z + b);
-        o[3] = *(const double*)((const char*)a.p.ux + b);
-        o[4] = *(const double*)((const char*)a.p.uy + b);
-        o[5] = *(const double*)((const char*)a.p.uz + b);
+        const unsigned j = a.perm ? a.perm[ip] : (unsigned)ip;
+        const unsigned b = j * 8u;
+        o[0] = *(const double*)((const char*)a.src.x + b);
+        o[1] = *(const double*)((const char*)a.src.y + b);
+        o[2] = *(const double*)((const char*)a.src.z + b);
+        o[3] = *(const double*)((const char*)a.src.ux + b);
+        o[4] = *(const double*)((const char*)a.src.uy + b);
+        o[5] = *(const double*)((const char*)a.src.uz + b);
     };
     {
         const int ip = p0 + (int)threadIdx.x;
@@ -488,12 +504,13 @@ push_deposit_kernel(const PDArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) xw[d] = wrap_coord(x1[d], L[d]);
                 const unsigned b = (unsigned)ip * 8u;
-                *(double*)((char*)a.p.x + b) = xw[0];
-                *(double*)((char*)a.p.y + b) = xw[1];
-                *(double*)((char*)a.p.z + b) = xw[2];
-                *(double*)((char*)a.p.ux + b) = u[0];
-                *(double*)((char*)a.p.uy + b) = u[1];
-                *(double*)((char*)a.p.uz + b) = u[2];
+                *(double*)((char*)a.dst.x + b) = xw[0];
+                *(double*)((char*)a.dst.y + b) = xw[1];
+                *(double*)((char*)a.dst.z + b) = xw[2];
+                *(double*)((char*)a.dst.ux + b) = u[0];
+                *(double*)((char*)a.dst.uy + b) = u[1];
+                *(double*)((char*)a.dst.uz + b) = u[2];
+                if (a.keys) a.keys[ip] = sort_key(g, xw);
             }
         }
 
@@ -564,8 +581,9 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
     unsigned long long cnt = 0;
     for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const int ip = a.far_q[i];
-        double x0[3] = {a.p.x[ip], a.p.y[ip], a.p.z[ip]};
-        double u[3] = {a.p.ux[ip], a.p.uy[ip], a.p.uz[ip]};
+        const unsigned j = a.perm ? a.perm[ip] : (unsigned)ip;
+        double x0[3] = {a.src.x[j], a.src.y[j], a.src.z[j]};
+        double u[3] = {a.src.ux[j], a.src.uy[j], a.src.uz[j]};
         double fl[3];
         int c0[3], c1[3];
 #pragma unroll
@@ -593,12 +611,15 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
         vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double vv) {
             unsafeAtomicAdd(&a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], vv);
         });
-        a.p.x[ip] = wrap_coord(x1[0], L[0]);
-        a.p.y[ip] = wrap_coord(x1[1], L[1]);
-        a.p.z[ip] = wrap_coord(x1[2], L[2]);
-        a.p.ux[ip] = u[0];
-        a.p.uy[ip] = u[1];
-        a.p.uz[ip] = u[2];
+        const double xw[3] = {wrap_coord(x1[0], L[0]), wrap_coord(x1[1], L[1]),
+                              wrap_coord(x1[2], L[2])};
+        a.dst.x[ip] = xw[0];
+        a.dst.y[ip] = xw[1];
+        a.dst.z[ip] = xw[2];
+        a.dst.ux[ip] = u[0];
+        a.dst.uy[ip] = u[1];
+        a.dst.uz[ip] = u[2];
+        if (a.keys) a.keys[ip] = sort_key(g, xw);
         cnt += 1;
     }
     if (cnt) atomicAdd(a.nfar, cnt);
@@ -639,14 +660,18 @@ int push_deposit_lds_bytes(const Geom& g) {
     return -1;
 }
 
-hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& p,
+hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& src,
+                               const Parts& dst, const unsigned* perm, unsigned* keys,
                                const int* sc_off, const Fields& f, double* const J[3],
                                unsigned* err, unsigned long long* nfar, int* far_q,
                                unsigned* far_n, unsigned* far_n_next, hipStream_t s) {
     PDArgs args;
     args.g = g;
     args.sp = sp;
-    args.p = p;
+    args.src = src;
+    args.dst = dst;
+    args.perm = perm;
+    args.keys = keys;
     args.sc_off = sc_off;
     for (int c = 0; c < 3; ++c) {
         args.EB[c] = f.E[c];

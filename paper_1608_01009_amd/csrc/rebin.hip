@@ -1,19 +1,21 @@
 // Re-sort of one species into supercell order (per-cell particle storage,
 // arXiv:1608.01009 Section 3, grouped by supercells, Section 4.3).
 //
-// key = supercell * S^3 + cell-in-supercell (both x-fastest), a stable sort
-// by key, implemented as an LSD radix sort of (key, index) pairs with 8-bit
-// digits.  Each pass:
-//   hist    per 4096-element block: digit histogram -> hist[digit][block]
-//   scan    exclusive scan over hist in (digit, block) order
-//   scatter per block: stable rank of every element among equal digits
-//           (wave-level ballot match, waves in order), write to its slot.
-// Stability of each pass gives a stable sort overall.  The supercell offsets
-// are taken from the sorted keys; then, inside every supercell, the cells'
-// particle lists are interleaved in rounds (round r holds the r-th particle of
-// every cell with more than r, in cell order), so that the 64 lanes of a wave
-// working through a round touch 64 different cells.  The final permutation is
-// applied to the SoA arrays and ids.
+// key = supercell * S^3 + cell-in-supercell (both x-fastest).  The keys are
+// written by the push of the step that precedes the re-sort (or computed here
+// from the positions when particles are loaded), then:
+//   1. a stable LSD radix sort of (key, index) pairs, passes of <= 11-bit
+//      digits (two passes up to 2^22 cells); each pass:
+//        hist    per 4096-element block: digit histogram -> hist[digit][block]
+//        scan    exclusive scan over hist in (digit, block) order
+//        scatter per block: stable rank among equal digits (wave-level ballot
+//                match, waves in element order), write to the slot;
+//   2. supercell offsets from the sorted keys;
+//   3. inside every supercell the cells' lists are interleaved in rounds:
+//      round r holds the r-th particle of every cell with more than r, cells
+//      in order, so that a wave working through a round touches 64 different
+//      cells.  The result is the permutation perm (new index -> old index).
+// The particle data are not moved here: the next push reads through perm.
 #include "pic_internal.h"
 
 namespace pic {
@@ -23,13 +25,13 @@ constexpr int kBlock = 256;          // 4 waves of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kRounds = 16;          // 64-element rounds per wave
 constexpr int kTile = kBlock * kRounds;  // 4096 elements per block
-constexpr int kDigits = 256;
+constexpr int kMaxBits = 11;
 
 __global__ void __launch_bounds__(kBlock) key_kernel(Geom g, int n, const double* x,
                                                      const double* y, const double* z,
                                                      const double* ux, const double* uy,
                                                      const double* uz, unsigned* key,
-                                                     unsigned* val, unsigned* err) {
+                                                     unsigned* err) {
     const int S = g.S;
     const int S3 = S * S * S;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -46,22 +48,23 @@ __global__ void __launch_bounds__(kBlock) key_kernel(Geom g, int n, const double
         const int sc = c[0] / S + g.ns[0] * (c[1] / S + g.ns[1] * (c[2] / S));
         const int loc = c[0] % S + S * (c[1] % S + S * (c[2] % S));
         key[i] = (unsigned)(sc * S3 + loc);
-        val[i] = (unsigned)i;
     }
 }
 
+template <int BITS>
 __global__ void __launch_bounds__(kBlock) hist_kernel(const unsigned* key, int n, int shift,
                                                       int nblocks, unsigned* hist) {
-    __shared__ unsigned cnt[kDigits];
-    cnt[threadIdx.x] = 0;
+    constexpr int D = 1 << BITS;
+    __shared__ unsigned cnt[D];
+    for (int d = threadIdx.x; d < D; d += kBlock) cnt[d] = 0;
     __syncthreads();
     const int b0 = blockIdx.x * kTile;
     for (int r = 0; r < kRounds; ++r) {
         const int i = b0 + r * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(key[i] >> shift) & (kDigits - 1)], 1u);
+        if (i < n) atomicAdd(&cnt[(key[i] >> shift) & (D - 1)], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    for (int d = threadIdx.x; d < D; d += kBlock) hist[d * nblocks + blockIdx.x] = cnt[d];
 }
 
 // Exclusive scan, three phases over chunks of kTile elements.
@@ -84,7 +87,7 @@ __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(const unsigned* in,
 }
 
 // Block-wide exclusive scan of one value per thread (Hillis-Steele in LDS).
-__device__ unsigned block_exscan(unsigned v, unsigned* tmp, unsigned* total) {
+__device__ unsigned block_exscan(unsigned v, unsigned* tmp) {
     tmp[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < kBlock; o <<= 1) {
@@ -94,7 +97,6 @@ __device__ unsigned block_exscan(unsigned v, unsigned* tmp, unsigned* total) {
         __syncthreads();
     }
     const unsigned incl = tmp[threadIdx.x];
-    if (total) *total = tmp[kBlock - 1];
     __syncthreads();
     return incl - v;
 }
@@ -102,7 +104,6 @@ __device__ unsigned block_exscan(unsigned v, unsigned* tmp, unsigned* total) {
 // Single workgroup: exclusive scan of up to kTile chunk sums, in place.
 __global__ void __launch_bounds__(kBlock) scan_sums_kernel(unsigned* sums, int m) {
     __shared__ unsigned tmp[kBlock];
-    // each thread owns kRounds consecutive entries
     unsigned local[kRounds];
     unsigned s = 0;
     for (int r = 0; r < kRounds; ++r) {
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) scan_sums_kernel(unsigned* sums, int m
         local[r] = (i < m) ? sums[i] : 0u;
         s += local[r];
     }
-    unsigned run = block_exscan(s, tmp, nullptr);
+    unsigned run = block_exscan(s, tmp);
     for (int r = 0; r < kRounds; ++r) {
         const int i = threadIdx.x * kRounds + r;
         if (i < m) sums[i] = run;
@@ -122,7 +123,6 @@ __global__ void __launch_bounds__(kBlock) scan_down_kernel(const unsigned* in, i
                                                            const unsigned* sums, unsigned* out) {
     __shared__ unsigned tmp[kBlock];
     const int b0 = blockIdx.x * kTile;
-    // thread t owns the kRounds consecutive entries b0 + t*kRounds + r
     unsigned local[kRounds];
     unsigned s = 0;
     for (int r = 0; r < kRounds; ++r) {
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) scan_down_kernel(const unsigned* in, i
         local[r] = (i < n) ? in[i] : 0u;
         s += local[r];
     }
-    unsigned run = block_exscan(s, tmp, nullptr) + sums[blockIdx.x];
+    unsigned run = block_exscan(s, tmp) + sums[blockIdx.x];
     for (int r = 0; r < kRounds; ++r) {
         const int i = b0 + threadIdx.x * kRounds + r;
         if (i < n) out[i] = run;
@@ -138,14 +138,17 @@ __global__ void __launch_bounds__(kBlock) scan_down_kernel(const unsigned* in, i
     }
 }
 
+// val_in == nullptr means the identity (val = element index).
+template <int BITS>
 __global__ void __launch_bounds__(kBlock) scatter_kernel(const unsigned* key_in,
                                                          const unsigned* val_in, int n, int shift,
                                                          int nblocks, const unsigned* offs,
                                                          unsigned* key_out, unsigned* val_out) {
-    __shared__ unsigned wcnt[kWaves][kDigits];
+    constexpr int D = 1 << BITS;
+    __shared__ unsigned wcnt[kWaves][D];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < kWaves * kDigits; d += kBlock) (&wcnt[0][0])[d] = 0;
+    for (int d = threadIdx.x; d < kWaves * D; d += kBlock) (&wcnt[0][0])[d] = 0;
     __syncthreads();
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int wbase = blockIdx.x * kTile + w * (kRounds * 64);
@@ -156,10 +159,10 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(const unsigned* key_in,
         const int i = wbase + r * 64 + lane;
         const bool valid = i < n;
         const unsigned k = valid ? key_in[i] : 0u;
-        const unsigned dgt = (k >> shift) & (kDigits - 1);
+        const unsigned dgt = (k >> shift) & (D - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             const unsigned long long bb = __ballot(valid && ((dgt >> b) & 1u));
             peers &= ((dgt >> b) & 1u) ? bb : ~bb;
         }
@@ -173,12 +176,12 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(const unsigned* key_in,
         if (valid && rank == 0) wcnt[w][dgt] = base + (unsigned)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
         kk[r] = k;
-        vv[r] = valid ? val_in[i] : 0u;
+        vv[r] = valid ? (val_in ? val_in[i] : (unsigned)i) : 0u;
         pos[r] = base + rank;
     }
     __syncthreads();
     // per digit: exclusive prefix over waves, plus the block's global offset
-    for (int d = threadIdx.x; d < kDigits; d += kBlock) {
+    for (int d = threadIdx.x; d < D; d += kBlock) {
         unsigned run = offs[d * nblocks + blockIdx.x];
         for (int ww = 0; ww < kWaves; ++ww) {
             const unsigned c = wcnt[ww][d];
@@ -190,10 +193,102 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(const unsigned* key_in,
     for (int r = 0; r < kRounds; ++r) {
         const int i = wbase + r * 64 + lane;
         if (i < n) {
-            const unsigned dgt = (kk[r] >> shift) & (kDigits - 1);
+            const unsigned dgt = (kk[r] >> shift) & (D - 1);
             const unsigned o = wcnt[w][dgt] + pos[r];
             key_out[o] = kk[r];
             val_out[o] = vv[r];
+        }
+    }
+}
+
+// sc_off[s] = first sorted index whose supercell is >= s; sc_off[nsc] = n.
+__global__ void __launch_bounds__(kBlock) offsets_kernel(const unsigned* key, int n, int S3,
+                                                         int nsc, int* sc_off) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i <= n; i += gridDim.x * kBlock) {
+        const int prev = (i == 0) ? -1 : (int)(key[i - 1] / (unsigned)S3);
+        const int cur = (i == n) ? nsc : (int)(key[i] / (unsigned)S3);
+        for (int s = prev + 1; s <= cur; ++s) sc_off[s] = i;
+    }
+}
+
+// One workgroup per supercell.  With cnt_l the particle count of cell l and
+// rank the position of a particle among its cell's particles, its place in the
+// round order is start + A[rank] + #{l < cell : cnt_l > rank}, where
+// A[r] = sum_l min(cnt_l, r).  For up to kMaxRounds rounds the per-round
+// masks of cells with cnt_l > r make that O(1) per particle.
+constexpr int kMaxS3 = 256;
+constexpr int kMaskWords = kMaxS3 / 64;
+constexpr int kMaxRounds = 512;
+
+__global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
+                                                            const unsigned* perm_sorted,
+                                                            const int* sc_off, int S3,
+                                                            unsigned* out) {
+    __shared__ int cnt[kMaxS3];
+    __shared__ int cst[kMaxS3];
+    __shared__ int rstart[kMaxRounds + 1];
+    __shared__ unsigned long long rmask[kMaxRounds][kMaskWords];
+    __shared__ int maxc_s;
+    const int sc = blockIdx.x;
+    const int s0 = sc_off[sc], s1 = sc_off[sc + 1];
+    if (s0 >= s1) return;
+    for (int l = threadIdx.x; l < S3; l += kBlock) cnt[l] = 0;
+    __syncthreads();
+    const unsigned kb = (unsigned)sc * (unsigned)S3;
+    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) atomicAdd(&cnt[key[i] - kb], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = s0, mx = 0;
+        for (int l = 0; l < S3; ++l) {
+            cst[l] = run;
+            run += cnt[l];
+            mx = cnt[l] > mx ? cnt[l] : mx;
+        }
+        maxc_s = mx;
+    }
+    __syncthreads();
+    const int maxc = maxc_s;
+    const int nwords = (S3 + 63) / 64;
+    if (maxc <= kMaxRounds) {
+        // round masks, then round starts (prefix of round sizes)
+        for (int r = threadIdx.x; r < maxc; r += kBlock) {
+            for (int w = 0; w < nwords; ++w) {
+                unsigned long long m = 0ull;
+                const int lend = (S3 - 64 * w) < 64 ? (S3 - 64 * w) : 64;
+                for (int b = 0; b < lend; ++b)
+                    if (cnt[64 * w + b] > r) m |= 1ull << b;
+                rmask[r][w] = m;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int r = 0; r < maxc; ++r) {
+                rstart[r] = run;
+                for (int w = 0; w < nwords; ++w) run += __popcll(rmask[r][w]);
+            }
+            rstart[maxc] = run;
+        }
+        __syncthreads();
+        for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
+            const int loc = (int)(key[i] - kb);
+            const int rank = i - cst[loc];
+            int pos = s0 + rstart[rank];
+            const int lw = loc >> 6, lb = loc & 63;
+            for (int w = 0; w < lw; ++w) pos += __popcll(rmask[rank][w]);
+            pos += __popcll(rmask[rank][lw] & ((1ull << lb) - 1ull));
+            out[pos] = perm_sorted ? perm_sorted[i] : (unsigned)i;
+        }
+    } else {
+        for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
+            const int loc = (int)(key[i] - kb);
+            const int rank = i - cst[loc];
+            int pos = s0;
+            for (int l = 0; l < S3; ++l) {
+                const int c = cnt[l];
+                pos += (c < rank ? c : rank) + ((l < loc && c > rank) ? 1 : 0);
+            }
+            out[pos] = perm_sorted ? perm_sorted[i] : (unsigned)i;
         }
     }
 }
@@ -212,52 +307,10 @@ __global__ void __launch_bounds__(kBlock) permute_kernel(int n, const unsigned* 
     }
 }
 
-// sc_off[s] = first sorted index whose supercell is >= s; sc_off[nsc] = n.
-__global__ void __launch_bounds__(kBlock) offsets_kernel(const unsigned* key, int n, int S3,
-                                                         int nsc, int* sc_off) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i <= n; i += gridDim.x * kBlock) {
-        const int prev = (i == 0) ? -1 : (int)(key[i - 1] / (unsigned)S3);
-        const int cur = (i == n) ? nsc : (int)(key[i] / (unsigned)S3);
-        for (int s = prev + 1; s <= cur; ++s) sc_off[s] = i;
-    }
-}
-
-// One workgroup per supercell: position of sorted element i in the round
-// order, pos = start + sum_l min(cnt_l, rank) + #{l < cell : cnt_l > rank}.
-constexpr int kMaxS3 = 512;
-
-__global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
-                                                            const unsigned* perm,
-                                                            const int* sc_off, int S3,
-                                                            unsigned* out) {
-    __shared__ int cnt[kMaxS3];
-    __shared__ int cst[kMaxS3];
-    const int sc = blockIdx.x;
-    const int s0 = sc_off[sc], s1 = sc_off[sc + 1];
-    if (s0 >= s1) return;
-    for (int l = threadIdx.x; l < S3; l += kBlock) cnt[l] = 0;
-    __syncthreads();
-    const unsigned kb = (unsigned)sc * (unsigned)S3;
-    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) atomicAdd(&cnt[key[i] - kb], 1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = s0;
-        for (int l = 0; l < S3; ++l) {
-            cst[l] = run;
-            run += cnt[l];
-        }
-    }
-    __syncthreads();
-    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
-        const int loc = (int)(key[i] - kb);
-        const int rank = i - cst[loc];
-        int pos = s0;
-        for (int l = 0; l < S3; ++l) {
-            const int c = cnt[l];
-            pos += (c < rank ? c : rank) + ((l < loc && c > rank) ? 1 : 0);
-        }
-        out[pos] = perm[i];
-    }
+__global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n, const unsigned* perm,
+                                                             const int64_t* src, int64_t* dst) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        dst[i] = src[perm[i]];
 }
 
 int nblk(int64_t n, int per) {
@@ -278,7 +331,8 @@ int key_bits(const Geom& g) {
     return b;
 }
 
-// scratch layout (unsigned words)
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
 struct Scratch {
     unsigned* k0;
     unsigned* v0;
@@ -289,11 +343,9 @@ struct Scratch {
     unsigned* sums;
 };
 
-size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
-
 Scratch carve(void* base, int64_t n) {
     const int nb = nblk(n, kTile);
-    const int64_t hn = (int64_t)kDigits * nb;
+    const int64_t hn = (int64_t)(1 << kMaxBits) * nb;
     char* p = (char*)base;
     Scratch s;
     const size_t kb = align_up((size_t)(n > 0 ? n : 1) * 4);
@@ -307,20 +359,54 @@ Scratch carve(void* base, int64_t n) {
     return s;
 }
 
+template <int BITS>
+void radix_pass(const unsigned* kin, const unsigned* vin, unsigned* kout, unsigned* vout, int n,
+                int shift, const Scratch& sc, hipStream_t s) {
+    const int nb = nblk(n, kTile);
+    const int hn = (1 << BITS) * nb;
+    const int nsum = nblk(hn, kTile);
+    hipLaunchKernelGGL((hist_kernel<BITS>), dim3(nb), dim3(kBlock), 0, s, kin, n, shift, nb,
+                       sc.hist);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn, sc.sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.sums, nsum);
+    hipLaunchKernelGGL(scan_down_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn, sc.sums,
+                       sc.offs);
+    hipLaunchKernelGGL((scatter_kernel<BITS>), dim3(nb), dim3(kBlock), 0, s, kin, vin, n, shift,
+                       nb, sc.offs, kout, vout);
+}
+
+void radix_pass_bits(int bits, const unsigned* kin, const unsigned* vin, unsigned* kout,
+                     unsigned* vout, int n, int shift, const Scratch& sc, hipStream_t s) {
+    switch (bits) {
+        case 1: radix_pass<1>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 2: radix_pass<2>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 3: radix_pass<3>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 4: radix_pass<4>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 5: radix_pass<5>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 6: radix_pass<6>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 7: radix_pass<7>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 8: radix_pass<8>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 9: radix_pass<9>(kin, vin, kout, vout, n, shift, sc, s); break;
+        case 10: radix_pass<10>(kin, vin, kout, vout, n, shift, sc, s); break;
+        default: radix_pass<11>(kin, vin, kout, vout, n, shift, sc, s); break;
+    }
+}
+
 }  // namespace
 
 size_t rebin_scratch_bytes(int64_t n, const Geom& g) {
     (void)g;
     const int nb = nblk(n, kTile);
-    const int64_t hn = (int64_t)kDigits * nb;
+    const int64_t hn = (int64_t)(1 << kMaxBits) * nb;
     const size_t kb = align_up((size_t)(n > 0 ? n : 1) * 4);
     return 4 * kb + 2 * align_up((size_t)hn * 4) + align_up((size_t)nblk(hn, kTile) * 4) + 256;
 }
 
-hipError_t launch_rebin(const Geom& g, int64_t n64, const Parts& src, const Parts& dst,
-                        int* sc_off, void* scratch, unsigned* err, hipStream_t s) {
+hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const Parts& src,
+                       unsigned* perm, int* sc_off, void* scratch, unsigned* err, hipStream_t s) {
     const int n = (int)n64;
     const int S3 = g.S * g.S * g.S;
+    if (S3 > kMaxS3) return hipErrorInvalidValue;
     if (n == 0) {
         hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kBlock), 0, s, (const unsigned*)nullptr,
                            0, S3, g.nsc, sc_off);
@@ -328,31 +414,57 @@ hipError_t launch_rebin(const Geom& g, int64_t n64, const Parts& src, const Part
     }
     Scratch sc = carve(scratch, n);
     const int nb = nblk(n, kTile);
-    const int hn = kDigits * nb;
-    const int nsum = nblk(hn, kTile);
+    const int nsum = nblk((int64_t)(1 << kMaxBits) * nb, kTile);
     if (nsum > kTile) return hipErrorInvalidValue;  // more than 2^24 histogram entries
-    hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, g, n, src.x, src.y,
-                       src.z, src.ux, src.uy, src.uz, sc.k0, sc.v0, err);
+    if (!keys) {
+        hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, g, n, src.x, src.y,
+                           src.z, src.ux, src.uy, src.uz, sc.k0, err);
+        keys = sc.k0;
+    }
     const int bits = key_bits(g);
-    unsigned *kin = sc.k0, *vin = sc.v0, *kout = sc.k1, *vout = sc.v1;
-    for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(hist_kernel, dim3(nb), dim3(kBlock), 0, s, kin, n, shift, nb, sc.hist);
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn,
-                           sc.sums);
-        hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.sums, nsum);
-        hipLaunchKernelGGL(scan_down_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn,
-                           sc.sums, sc.offs);
-        hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(kBlock), 0, s, kin, vin, n, shift, nb,
-                           sc.offs, kout, vout);
-        unsigned* t = kin; kin = kout; kout = t;
-        t = vin; vin = vout; vout = t;
+    const int npass = (bits + kMaxBits - 1) / kMaxBits;
+    // pass p reads the previous pass's output (the input keys and the
+    // identity for p = 0) and writes (k1, v1) for even p, (k0, v0) for odd p
+    const unsigned* kin = keys;
+    const unsigned* vin = nullptr;  // identity
+    unsigned* kbuf[2] = {sc.k1, sc.k0};
+    unsigned* vbuf[2] = {sc.v1, sc.v0};
+    int shift = 0;
+    for (int p = 0; p < npass; ++p) {
+        const int width = (bits - shift + (npass - p) - 1) / (npass - p);
+        radix_pass_bits(width, kin, vin, kbuf[p & 1], vbuf[p & 1], n, shift, sc, s);
+        kin = kbuf[p & 1];
+        vin = vbuf[p & 1];
+        shift += width;
+    }
+    if (npass == 0) {
+        // a single cell: the sorted order is the input order
+        hipLaunchKernelGGL(offsets_kernel, dim3(grid_for((int64_t)n + 1)), dim3(kBlock), 0, s,
+                           keys, n, S3, g.nsc, sc_off);
+        hipLaunchKernelGGL(interleave_kernel, dim3(g.nsc), dim3(kBlock), 0, s, keys,
+                           (const unsigned*)nullptr, sc_off, S3, perm);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(offsets_kernel, dim3(grid_for((int64_t)n + 1)), dim3(kBlock), 0, s, kin, n,
                        S3, g.nsc, sc_off);
-    if (S3 > kMaxS3) return hipErrorInvalidValue;
     hipLaunchKernelGGL(interleave_kernel, dim3(g.nsc), dim3(kBlock), 0, s, kin, vin, sc_off, S3,
-                       kout);
-    hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, kout, src, dst);
+                       perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, const Parts& dst,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, (int)n, perm, src,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_ids(int64_t n, const unsigned* perm, const int64_t* src, int64_t* dst,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_ids_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, (int)n, perm,
+                       src, dst);
     return hipGetLastError();
 }
 
