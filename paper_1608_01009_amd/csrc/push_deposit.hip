@@ -126,7 +126,17 @@ __device__ __forceinline__ void vb_segment(const double A[3], const double B[3],
 
 // Sort key of a stored (wrapped) position: supercell * S^3 + cell in
 // supercell, both x-fastest.
+template <int S>
 __device__ __forceinline__ unsigned sort_key(const Geom& g, const double x[3]) {
+    int c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = (int)floor(x[d]);
+    const int sc = c[0] / S + g.ns[0] * (c[1] / S + g.ns[1] * (c[2] / S));
+    const int loc = c[0] % S + S * (c[1] % S + S * (c[2] % S));
+    return (unsigned)(sc * S * S * S + loc);
+}
+
+__device__ __forceinline__ unsigned sort_key_rt(const Geom& g, const double x[3]) {
     const int S = g.S;
     int c[3];
 #pragma unroll
@@ -277,6 +287,63 @@ __device__ __forceinline__ void gather6(const Stencil& st, const int off[3], con
                  st.fh[0], st.fh[1], st.f0[2]);
 }
 
+// Tile gather of the six components.  Component k+1's eight values are
+// loaded before component k is interpolated, so LDS latency overlaps the FMA
+// chain with two components (32 VGPRs) in flight.  Same nested-lerp order as
+// cic8: v[a + 2 b + 4 c] = F(a, b, c), x first, then y, then z.
+struct Oct {
+    double v[8];
+};
+
+template <int T>
+__device__ __forceinline__ Oct ld_oct(const double* eb, int base) {
+    constexpr int T2 = T * T;
+    const double* p = eb + base;
+    Oct o;
+    o.v[0] = p[0];
+    o.v[1] = p[1];
+    o.v[2] = p[T];
+    o.v[3] = p[T + 1];
+    o.v[4] = p[T2];
+    o.v[5] = p[T2 + 1];
+    o.v[6] = p[T2 + T];
+    o.v[7] = p[T2 + T + 1];
+    return o;
+}
+
+__device__ __forceinline__ double interp_oct(const Oct& o, double fx, double fy, double fz) {
+#pragma clang fp contract(off)
+    const double q00 = __fma_rn(fx, o.v[1] - o.v[0], o.v[0]);
+    const double q10 = __fma_rn(fx, o.v[3] - o.v[2], o.v[2]);
+    const double q01 = __fma_rn(fx, o.v[5] - o.v[4], o.v[4]);
+    const double q11 = __fma_rn(fx, o.v[7] - o.v[6], o.v[6]);
+    const double r0 = __fma_rn(fy, q10 - q00, q00);
+    const double r1 = __fma_rn(fy, q11 - q01, q01);
+    return __fma_rn(fz, r1 - r0, r0);
+}
+
+template <int T>
+__device__ __forceinline__ void gather_tile(const double* eb, const Stencil& st, const int off[3],
+                                            double E[3], double Bf[3]) {
+    constexpr int T2 = T * T, T3 = T2 * T;
+    const int x0 = st.i0[0] + off[0], y0 = st.i0[1] + off[1], z0 = st.i0[2] + off[2];
+    const int xh = st.ih[0] + off[0], yh = st.ih[1] + off[1], zh = st.ih[2] + off[2];
+    // Yee stagger per component: Ex (h,0,0) Ey (0,h,0) Ez (0,0,h)
+    //                            Bx (0,h,h) By (h,0,h) Bz (h,h,0)
+    Oct a = ld_oct<T>(eb, 0 * T3 + xh + T * y0 + T2 * z0);
+    Oct b = ld_oct<T>(eb, 1 * T3 + x0 + T * yh + T2 * z0);
+    E[0] = interp_oct(a, st.fh[0], st.f0[1], st.f0[2]);
+    a = ld_oct<T>(eb, 2 * T3 + x0 + T * y0 + T2 * zh);
+    E[1] = interp_oct(b, st.f0[0], st.fh[1], st.f0[2]);
+    b = ld_oct<T>(eb, 3 * T3 + x0 + T * yh + T2 * zh);
+    E[2] = interp_oct(a, st.f0[0], st.f0[1], st.fh[2]);
+    a = ld_oct<T>(eb, 4 * T3 + xh + T * y0 + T2 * zh);
+    Bf[0] = interp_oct(b, st.f0[0], st.fh[1], st.fh[2]);
+    b = ld_oct<T>(eb, 5 * T3 + xh + T * yh + T2 * z0);
+    Bf[1] = interp_oct(a, st.fh[0], st.f0[1], st.fh[2]);
+    Bf[2] = interp_oct(b, st.fh[0], st.fh[1], st.f0[2]);
+}
+
 __device__ __forceinline__ bool finite3(double a, double b, double c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
@@ -336,7 +403,9 @@ __device__ __forceinline__ constexpr int jt_off(int j) {
     return d * JC + bp * sp + br * sr;
 }
 
-template <int S, int H>
+// GATHER: particle i of this step is read from src at perm[i] (the step after
+// a re-sort), otherwise at i.
+template <int S, int H, bool GATHER>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 push_deposit_kernel(const PDArgs a) {
     constexpr int T = S + 2 * H + 2;   // E/B tile edge in nodes
@@ -431,7 +500,7 @@ push_deposit_kernel(const PDArgs a) {
     // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
     // six loads and six stores of a particle share one offset register.
     auto ld6 = [&](int ip, double o[6]) {
-        const unsigned j = a.perm ? a.perm[ip] : (unsigned)ip;
+        const unsigned j = GATHER ? a.perm[ip] : (unsigned)ip;
         const unsigned b = j * 8u;
         o[0] = *(const double*)((const char*)a.src.x + b);
         o[1] = *(const double*)((const char*)a.src.y + b);
@@ -456,7 +525,10 @@ push_deposit_kernel(const PDArgs a) {
         bool crosser = false, far = false;
         double x1[3] = {0.0, 0.0, 0.0};
         if (valid) {
-            bool ok = finite3(x0[0], x0[1], x0[2]) && finite3(u[0], u[1], u[2]);
+            // stored positions lie in [0, L) (this also rejects NaN); a
+            // non-finite momentum shows up in the pushed state checked below
+            bool ok = (x0[0] >= 0.0 && x0[0] < L[0]) && (x0[1] >= 0.0 && x0[1] < L[1]) &&
+                      (x0[2] >= 0.0 && x0[2] < L[2]);
             double fl[3];
             int c0[3], rel[3];
 #pragma unroll
@@ -473,11 +545,7 @@ push_deposit_kernel(const PDArgs a) {
                 int off[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) off[d] = rel[d] + H + 1 - c0[d];
-                gather6(st, off,
-                        [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
-                            return eb[comp * T3 + (ix + da) + T * (iy + db) + T2 * (iz + dc)];
-                        },
-                        E, Bf);
+                gather_tile<T>(eb, st, off, E, Bf);
                 boris_advance(a.sp, g, E, Bf, u, x0, x1);
                 ok = finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]);
             }
@@ -510,7 +578,7 @@ push_deposit_kernel(const PDArgs a) {
                 *(double*)((char*)a.dst.ux + b) = u[0];
                 *(double*)((char*)a.dst.uy + b) = u[1];
                 *(double*)((char*)a.dst.uz + b) = u[2];
-                if (a.keys) a.keys[ip] = sort_key(g, xw);
+                if (a.keys) a.keys[ip] = sort_key<S>(g, xw);
             }
         }
 
@@ -619,7 +687,7 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
         a.dst.ux[ip] = u[0];
         a.dst.uy[ip] = u[1];
         a.dst.uz[ip] = u[2];
-        if (a.keys) a.keys[ip] = sort_key(g, xw);
+        if (a.keys) a.keys[ip] = sort_key_rt(g, xw);
         cnt += 1;
     }
     if (cnt) atomicAdd(a.nfar, cnt);
@@ -627,7 +695,12 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
 
 template <int S, int H>
 hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
-    hipLaunchKernelGGL((push_deposit_kernel<S, H>), dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+    if (args.perm)
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true>), dim3(args.g.nsc), dim3(kBlock), 0, s,
+                           args);
+    else
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false>), dim3(args.g.nsc), dim3(kBlock), 0,
+                           s, args);
     hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
