@@ -82,37 +82,45 @@ void orc_gather(const orc_grid* g, const double* const EB[6], const double xp[3]
  *   u- = u + h E;  gamma- = sqrt(1 + |u-|^2)
  *   t = (h / gamma-) B;  s = 2 t / (1 + |t|^2)
  *   u' = u- + u- x t;  u+ = u- + u' x s;  u_new = u+ + h E
+ * The paper fixes no evaluation order.  Each sum of products is evaluated
+ * as a chain of fused multiply-adds (one rounding per product-add):
+ *   1 + |v|^2          = fma(v2, v2, fma(v1, v1, fma(v0, v0, 1)))
+ *   a0 + (b1 c2 - b2 c1) = fma(b1, c2, fma(-b2, c1, a0))   (cross products)
+ *   u + h E            = fma(h, E, u)
  * ------------------------------------------------------------------------- */
+static double one_plus_sq(const double v[3]) {
+    return fma(v[2], v[2], fma(v[1], v[1], fma(v[0], v[0], 1.0)));
+}
+
+/* a + b x c, component d, as two fused multiply-adds */
+static double add_cross(const double a[3], const double b[3], const double c[3], int d) {
+    const int e = (d + 1) % 3, f = (d + 2) % 3;
+    return fma(b[e], c[f], fma(-b[f], c[e], a[d]));
+}
+
 void orc_boris(double q, double m, double dt, const double EB[6], double u[3]) {
     const double h = (q * dt) / (2.0 * m);
     const double* E = EB;
     const double* B = EB + 3;
     double um[3], t[3], s[3], up[3], upl[3];
-    for (int d = 0; d < 3; ++d) um[d] = u[d] + h * E[d];
-    double g2 = 1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]);
-    double gm = sqrt(g2);
+    for (int d = 0; d < 3; ++d) um[d] = fma(h, E[d], u[d]);
+    double gm = sqrt(one_plus_sq(um));
     double hg = h / gm;
     for (int d = 0; d < 3; ++d) t[d] = hg * B[d];
-    double t2 = (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2];
-    double sf = 2.0 / (1.0 + t2);
+    double sf = 2.0 / one_plus_sq(t);
     for (int d = 0; d < 3; ++d) s[d] = sf * t[d];
-    /* u' = u- + u- x t */
-    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
-    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
-    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
-    /* u+ = u- + u' x s */
-    upl[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
-    upl[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
-    upl[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
-    for (int d = 0; d < 3; ++d) u[d] = upl[d] + h * E[d];
+    for (int d = 0; d < 3; ++d) up[d] = add_cross(um, um, t, d);   /* u' = u- + u- x t */
+    for (int d = 0; d < 3; ++d) upl[d] = add_cross(um, up, s, d);  /* u+ = u- + u' x s */
+    for (int d = 0; d < 3; ++d) u[d] = fma(h, E[d], upl[d]);
 }
 
-/* x*_d = x_d + ((dt/dx_d) u_d) g,  g = 1 / sqrt(1 + |u|^2); unwrapped. */
+/* x*_d = x_d + ((dt/dx_d) u_d) g,  g = 1 / sqrt(1 + |u|^2); unwrapped; the
+ * final product-add is fused. */
 void orc_advance(const orc_grid* g, const double u[3], const double x[3], double xs[3]) {
-    double gi = 1.0 / sqrt(1.0 + ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]));
+    double gi = 1.0 / sqrt(one_plus_sq(u));
     for (int d = 0; d < 3; ++d) {
         double cdt = g->dt / g->dx[d];
-        xs[d] = x[d] + (cdt * u[d]) * gi;
+        xs[d] = fma(cdt * u[d], gi, x[d]);
     }
 }
 

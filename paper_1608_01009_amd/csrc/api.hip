@@ -272,6 +272,11 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
             return bad("species charge must be finite, mass and weight finite and > 0");
         if (q.capacity < 0 || q.capacity >= (int64_t(1) << 29))
             return bad("species capacity must be in [0, 2^29)");
+        // the Boris kick h = q dt / (2 m) enters a division whose operand
+        // ranges the push kernel relies on
+        const double hq = std::fabs((q.charge * dt) / (2.0 * q.mass));
+        if (hq != 0.0 && !(hq > 0x1p-900 && hq < 0x1p900))
+            return bad("|charge dt / (2 mass)| must be 0 or within (2^-900, 2^900)");
     }
 
     pic_ctx* c = new (std::nothrow) pic_ctx();

@@ -18,10 +18,11 @@
 // Particles that drifted further than the halo since the last re-sort take a
 // global-memory path (gather from global E/B, global atomics for J).
 //
-// Gather, Boris and advance are evaluated in exactly the expression order of
-// the textbook formulas with floating-point contraction off, so positions and
-// momenta are reproducible bit for bit by any IEEE FP64 evaluation of the same
-// formulas.
+// Gather, Boris and advance are evaluated in a fixed expression order (fused
+// multiply-adds exactly where written, contraction off elsewhere, correctly
+// rounded square roots and divisions), so positions and momenta are
+// reproducible bit for bit by any IEEE FP64 evaluation of the same
+// expressions.
 #include "pic_internal.h"
 
 namespace pic {
@@ -204,6 +205,56 @@ __device__ __forceinline__ void vb_move(const double x0[3], const double x1[3], 
 }
 
 // Relativistic Boris rotation, then the position advance (unwrapped).
+// Square root of x >= 1 (finite), correctly rounded: the reciprocal square
+// root estimate refined by Newton steps and two fused residual corrections.
+// These are the operations of the general IEEE FP64 square root of gfx9 less
+// its range scaling, which is the identity for x >= 1, so the result is the
+// same bit for bit.
+__device__ __forceinline__ double sqrt_ge1(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = __fma_rn(-h, g, 0.5);
+    g = __fma_rn(g, r, g);
+    h = __fma_rn(h, r, h);
+    double d = __fma_rn(-g, g, x);
+    g = __fma_rn(d, h, g);
+    d = __fma_rn(-g, g, x);
+    return __fma_rn(d, h, g);
+}
+
+// a / b, correctly rounded, for 1 <= b < 2^1000 and a = 0 or
+// 2^-900 < |a| < 2^900: reciprocal estimate, two Newton steps, quotient and
+// one fused residual correction.  Again the operations of the general IEEE
+// FP64 division less its range scaling and special-case fix-up, neither of
+// which acts on operands in these ranges.
+__device__ __forceinline__ double div_ge1(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = __fma_rn(-b, r, 1.0);
+    r = __fma_rn(r, e, r);
+    e = __fma_rn(-b, r, 1.0);
+    r = __fma_rn(r, e, r);
+    const double q = a * r;
+    e = __fma_rn(-b, q, a);
+    return __fma_rn(e, r, q);
+}
+
+__device__ __forceinline__ double one_plus_sq(const double v[3]) {
+    return __fma_rn(v[2], v[2], __fma_rn(v[1], v[1], __fma_rn(v[0], v[0], 1.0)));
+}
+
+// component d of a + b x c, as two fused multiply-adds
+__device__ __forceinline__ double add_cross(const double a[3], const double b[3],
+                                            const double c[3], int d) {
+    const int e = (d + 1) % 3, f = (d + 2) % 3;
+    return __fma_rn(b[e], c[f], __fma_rn(-b[f], c[e], a[d]));
+}
+
+// Boris rotation (half E kick, B rotation, half E kick) and the straight
+// position advance x1 = x0 + (dt/dx_d) u_d / gamma.  Every sum of products is
+// a chain of fused multiply-adds in a fixed order; gamma- >= 1 and
+// 1 + |t|^2 >= 1 keep the square roots and divisions in the ranges of
+// sqrt_ge1 and div_ge1 (|q dt / 2m| is range-checked when a context is
+// created).
 __device__ __forceinline__ void boris_advance(const SpeciesC& sp, const Geom& g, const double E[3],
                                               const double Bf[3], double u[3], const double x0[3],
                                               double x1[3]) {
@@ -211,27 +262,22 @@ __device__ __forceinline__ void boris_advance(const SpeciesC& sp, const Geom& g,
     const double h = sp.hq;
     double um[3], t[3], s[3], up[3], upl[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) um[d] = u[d] + h * E[d];
-    const double g2 = 1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]);
-    const double gm = sqrt(g2);
-    const double hg = h / gm;
+    for (int d = 0; d < 3; ++d) um[d] = __fma_rn(h, E[d], u[d]);
+    const double hg = div_ge1(h, sqrt_ge1(one_plus_sq(um)));
 #pragma unroll
     for (int d = 0; d < 3; ++d) t[d] = hg * Bf[d];
-    const double tt = (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2];
-    const double sf = 2.0 / (1.0 + tt);
+    const double sf = div_ge1(2.0, one_plus_sq(t));
 #pragma unroll
     for (int d = 0; d < 3; ++d) s[d] = sf * t[d];
-    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
-    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
-    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
-    upl[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
-    upl[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
-    upl[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = upl[d] + h * E[d];
-    const double gi = 1.0 / sqrt(1.0 + ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]));
+    for (int d = 0; d < 3; ++d) up[d] = add_cross(um, um, t, d);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) x1[d] = x0[d] + (g.cdt[d] * u[d]) * gi;
+    for (int d = 0; d < 3; ++d) upl[d] = add_cross(um, up, s, d);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = __fma_rn(h, E[d], upl[d]);
+    const double gi = div_ge1(1.0, sqrt_ge1(one_plus_sq(u)));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x1[d] = __fma_rn(g.cdt[d] * u[d], gi, x0[d]);
 }
 
 __device__ __forceinline__ double wrap_coord(double v, double L) {
@@ -298,7 +344,15 @@ struct Oct {
 template <int T>
 __device__ __forceinline__ Oct ld_oct(const double* eb, int base) {
     constexpr int T2 = T * T;
-    const double* p = eb + base;
+    // One address register per component (hiding the index from constant
+    // folding keeps the component offset out of the loads, which then take
+    // immediate offsets).  The loads are volatile so that they stay eight
+    // single ds_read_b64: for the scattered addresses of a round of
+    // particles, pairing them into ds_read2_b64 costs more LDS cycles than
+    // the two single reads.
+    asm volatile("" : "+v"(base));
+    typedef __attribute__((address_space(3))) const volatile double lds_double;
+    const lds_double* p = (const lds_double*)(eb + base);
     Oct o;
     o.v[0] = p[0];
     o.v[1] = p[1];

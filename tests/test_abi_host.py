@@ -55,6 +55,8 @@ def _create(**kw):
     (dict(species=[(-1.0, 0.0, 0.1, 10)]), "mass"),
     (dict(species=[(-1.0, 1.0, -0.1, 10)]), "weight"),
     (dict(species=[(-1.0, 1.0, 0.1, -1)]), "capacity"),
+    (dict(species=[(1e-280, 1.0, 0.1, 10)]), "charge dt"),
+    (dict(species=[(-1.0, 1e-280, 0.1, 10)]), "charge dt"),
     (dict(species=[]), "n_species"),
 ])
 def test_create_rejects_invalid_arguments(kw, needle):
