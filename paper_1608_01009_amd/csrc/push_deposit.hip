@@ -37,6 +37,23 @@ __device__ __forceinline__ int wrapi(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
+// i mod n for i in [-n, 2n)
+__device__ __forceinline__ int near_wrap(int i, int n) {
+    i = i < 0 ? i + n : i;
+    return i >= n ? i - n : i;
+}
+
+// Global linear index of tile node (tx, ty, tz) with tile origin org: the
+// coordinates lie in [-n, 2n) when every n_d >= h + 2 (uniform flag `near`),
+// otherwise they are reduced with a full modulo.
+__device__ __forceinline__ int tile_node_index(const int org[3], int tx, int ty, int tz, int nx,
+                                               int ny, int nz, bool near) {
+    if (near)
+        return near_wrap(org[0] + tx, nx) +
+               nx * (near_wrap(org[1] + ty, ny) + ny * near_wrap(org[2] + tz, nz));
+    return wrapi(org[0] + tx, nx) + nx * (wrapi(org[1] + ty, ny) + ny * wrapi(org[2] + tz, nz));
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X.  Map
 // them so that each XCD receives a contiguous range of supercells: the
 // overlapping halos of neighbouring tiles are then read and atomically
@@ -341,9 +358,8 @@ struct Oct {
     double v[8];
 };
 
-template <int T>
+template <int PY, int PZ>
 __device__ __forceinline__ Oct ld_oct(const double* eb, int base) {
-    constexpr int T2 = T * T;
     // One address register per component (hiding the index from constant
     // folding keeps the component offset out of the loads, which then take
     // immediate offsets).  The loads are volatile so that they stay eight
@@ -356,12 +372,12 @@ __device__ __forceinline__ Oct ld_oct(const double* eb, int base) {
     Oct o;
     o.v[0] = p[0];
     o.v[1] = p[1];
-    o.v[2] = p[T];
-    o.v[3] = p[T + 1];
-    o.v[4] = p[T2];
-    o.v[5] = p[T2 + 1];
-    o.v[6] = p[T2 + T];
-    o.v[7] = p[T2 + T + 1];
+    o.v[2] = p[PY];
+    o.v[3] = p[PY + 1];
+    o.v[4] = p[PZ];
+    o.v[5] = p[PZ + 1];
+    o.v[6] = p[PZ + PY];
+    o.v[7] = p[PZ + PY + 1];
     return o;
 }
 
@@ -376,24 +392,24 @@ __device__ __forceinline__ double interp_oct(const Oct& o, double fx, double fy,
     return __fma_rn(fz, r1 - r0, r0);
 }
 
-template <int T>
+template <class EL>
 __device__ __forceinline__ void gather_tile(const double* eb, const Stencil& st, const int off[3],
                                             double E[3], double Bf[3]) {
-    constexpr int T2 = T * T, T3 = T2 * T;
+    constexpr int PY = EL::PY, PZ = EL::PZ, CS = EL::CS;
     const int x0 = st.i0[0] + off[0], y0 = st.i0[1] + off[1], z0 = st.i0[2] + off[2];
     const int xh = st.ih[0] + off[0], yh = st.ih[1] + off[1], zh = st.ih[2] + off[2];
     // Yee stagger per component: Ex (h,0,0) Ey (0,h,0) Ez (0,0,h)
     //                            Bx (0,h,h) By (h,0,h) Bz (h,h,0)
-    Oct a = ld_oct<T>(eb, 0 * T3 + xh + T * y0 + T2 * z0);
-    Oct b = ld_oct<T>(eb, 1 * T3 + x0 + T * yh + T2 * z0);
+    Oct a = ld_oct<PY, PZ>(eb, 0 * CS + xh + PY * y0 + PZ * z0);
+    Oct b = ld_oct<PY, PZ>(eb, 1 * CS + x0 + PY * yh + PZ * z0);
     E[0] = interp_oct(a, st.fh[0], st.f0[1], st.f0[2]);
-    a = ld_oct<T>(eb, 2 * T3 + x0 + T * y0 + T2 * zh);
+    a = ld_oct<PY, PZ>(eb, 2 * CS + x0 + PY * y0 + PZ * zh);
     E[1] = interp_oct(b, st.f0[0], st.fh[1], st.f0[2]);
-    b = ld_oct<T>(eb, 3 * T3 + x0 + T * yh + T2 * zh);
+    b = ld_oct<PY, PZ>(eb, 3 * CS + x0 + PY * yh + PZ * zh);
     E[2] = interp_oct(a, st.f0[0], st.f0[1], st.fh[2]);
-    a = ld_oct<T>(eb, 4 * T3 + xh + T * y0 + T2 * zh);
+    a = ld_oct<PY, PZ>(eb, 4 * CS + xh + PY * y0 + PZ * zh);
     Bf[0] = interp_oct(b, st.f0[0], st.fh[1], st.fh[2]);
-    b = ld_oct<T>(eb, 5 * T3 + xh + T * yh + T2 * z0);
+    b = ld_oct<PY, PZ>(eb, 5 * CS + xh + PY * yh + PZ * z0);
     Bf[1] = interp_oct(a, st.fh[0], st.f0[1], st.fh[2]);
     Bf[2] = interp_oct(b, st.fh[0], st.fh[1], st.f0[2]);
 }
@@ -433,6 +449,19 @@ __device__ __forceinline__ void vb_single(const double x0[3], const double x1[3]
     }
 }
 
+// Layout of the E/B tile in LDS: node (tx, ty, tz) of component c lives at
+// c * CS + tx + PY * ty + PZ * tz.  For S = 4 the plane pitch is padded from
+// 64 to 68 doubles, which spreads the stencils of the lanes of a round (two
+// z-layers of the supercell per half wave, each lane shifted by the
+// component's stagger) over more LDS banks.
+template <int S, int H>
+struct EBLayout {
+    static constexpr int T = S + 2 * H + 2;
+    static constexpr int PY = T;
+    static constexpr int PZ = (S == 4) ? T * T + 4 : T * T;
+    static constexpr int CS = PZ * T;  // doubles per component
+};
+
 // Layout of the J tile in LDS: node (tx, ty, tz) of component d lives at
 // d * JC + tx + PY * ty + PZ * tz.  For S = 4 the pitches are padded so that
 // the 32 cells of a half wave (one round covers the 64 cells of the
@@ -462,14 +491,15 @@ __device__ __forceinline__ constexpr int jt_off(int j) {
 template <int S, int H, bool GATHER>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 push_deposit_kernel(const PDArgs a) {
-    constexpr int T = S + 2 * H + 2;   // E/B tile edge in nodes
+    using EL = EBLayout<S, H>;
+    constexpr int T = EL::T;           // E/B tile edge in nodes
     constexpr int T2 = T * T, T3 = T2 * T;
     using JL = JLayout<S, H>;
     constexpr int TJ = JL::TJ;         // J tile edge in nodes
     constexpr int PY = JL::PY, PZ = JL::PZ, JC = JL::JC;
     constexpr int kWaves = kBlock / 64;
     constexpr int QCAP = 28;           // queued cell-crossing particles per wave
-    __shared__ double eb[6 * T3];
+    __shared__ double eb[6 * EL::CS];
     __shared__ double jt[3 * JC];
     __shared__ double qb[kWaves][6][QCAP];
 
@@ -484,17 +514,19 @@ push_deposit_kernel(const PDArgs a) {
     const int sy = syz % g.ns[1], sz = syz / g.ns[1];
     const int base[3] = {sx * S, sy * S, sz * S};          // first cell of the supercell
     const int org[3] = {base[0] - H - 1, base[1] - H - 1, base[2] - H - 1};  // tile origin
+    const bool near = nx >= H + 2 && ny >= H + 2 && nz >= H + 2;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    for (int t = threadIdx.x; t < 6 * T3; t += kBlock) {
-        const int c = t / T3;
-        const int r = t - c * T3;
+    // E/B tile: one wrapped global index per node, shared by the six
+    // components (tile coordinates lie within one period of [0, n))
+    for (int r = threadIdx.x; r < T3; r += kBlock) {
         const int tz = r / T2, ty = (r / T) % T, tx = r % T;
-        const int gx = wrapi(org[0] + tx, nx), gy = wrapi(org[1] + ty, ny),
-                  gz = wrapi(org[2] + tz, nz);
-        eb[t] = a.EB[c][gx + nx * (gy + ny * gz)];
+        const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+        const int li = tx + EL::PY * ty + EL::PZ * tz;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = a.EB[c][gi];
     }
     for (int t = threadIdx.x; t < 3 * JC; t += kBlock) jt[t] = 0.0;
     __syncthreads();
@@ -599,7 +631,7 @@ push_deposit_kernel(const PDArgs a) {
                 int off[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) off[d] = rel[d] + H + 1 - c0[d];
-                gather_tile<T>(eb, st, off, E, Bf);
+                gather_tile<EL>(eb, st, off, E, Bf);
                 boris_advance(a.sp, g, E, Bf, u, x0, x1);
                 ok = finite3(u[0], u[1], u[2]) && finite3(x1[0], x1[1], x1[2]);
             }
@@ -678,15 +710,15 @@ push_deposit_kernel(const PDArgs a) {
     __syncthreads();
 
     constexpr int TJ2 = TJ * TJ, TJ3 = TJ2 * TJ;
-    for (int t = threadIdx.x; t < 3 * TJ3; t += kBlock) {
-        const int c = t / TJ3;
-        const int r = t - c * TJ3;
+    for (int r = threadIdx.x; r < TJ3; r += kBlock) {
         const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
-        const double v = jt[c * JC + tx + PY * ty + PZ * tz];
-        if (v != 0.0) {
-            const int gx = wrapi(org[0] + tx, nx), gy = wrapi(org[1] + ty, ny),
-                      gz = wrapi(org[2] + tz, nz);
-            unsafeAtomicAdd(&a.J[c][gx + nx * (gy + ny * gz)], v);
+        const int li = tx + PY * ty + PZ * tz;
+        const double v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
+        if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) {
+            const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (v[c] != 0.0) unsafeAtomicAdd(&a.J[c][gi], v[c]);
         }
     }
 }
@@ -761,7 +793,7 @@ hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
 
 template <int S, int H>
 constexpr int lds_bytes_sh() {
-    return (6 * (S + 2 * H + 2) * (S + 2 * H + 2) * (S + 2 * H + 2) + 3 * JLayout<S, H>::JC +
+    return (6 * EBLayout<S, H>::CS + 3 * JLayout<S, H>::JC +
             (kBlock / 64) * 6 * 28) *
            (int)sizeof(double);
 }

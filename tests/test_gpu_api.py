@@ -145,7 +145,7 @@ def test_timers_and_counters():
     c = sim.counters()
     assert c[1] == 1 and c[2] == 25
     # E/B tile 8^3 x 6, padded J tile 3 x 1001, crosser queues 8 waves x 6 x 28 doubles
-    assert c[3] == (6 * 512 + 3 * 1001 + 8 * 6 * 28) * 8
+    assert c[3] == (6 * 544 + 3 * 1001 + 8 * 6 * 28) * 8    # E/B tile, J tile, crosser queues
     sim.close()
 
 
