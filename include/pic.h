@@ -79,8 +79,9 @@ typedef struct {
 
 /* Create a context on the current HIP device.  dx[3] > 0 are the cell sizes,
  * dt > 0 must not exceed the Yee limit 1/sqrt(sum 1/dx_d^2).  Allocates all
- * device memory (particles twice over for the re-sort, fields, currents,
- * sort scratch).  Fields start at zero.  *out receives the context. */
+ * device memory (particles twice over for the re-sort, E and B twice over for
+ * the out-of-place Yee update, currents, sort scratch).  Fields start at
+ * zero.  *out receives the context. */
 int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                const pic_species_t* species, int32_t n_species, pic_ctx** out);
 
@@ -124,10 +125,17 @@ int pic_diagnostics(pic_ctx* ctx, double out[8]);
  * pic_enable_timers(ctx, 1) turns them on and resets them. */
 int pic_enable_timers(pic_ctx* ctx, int32_t on);
 
-/* ms[0] push+deposit (gather, Boris, advance, VB deposit into LDS tiles and
- * their flush), ms[1] Yee update, ms[2] re-sort, ms[3] total of pic_step
- * calls; ms[4] number of push+deposit launches, ms[5] number of steps. */
-int pic_get_timers(pic_ctx* ctx, double ms[6]);
+/* Milliseconds summed over the timed steps, and launch counts:
+ *   ms[0] push+deposit kernel (gather, Boris, advance, VB deposit into the
+ *         LDS tiles and their flush) reading the particles in stored order,
+ *   ms[1] number of those launches,
+ *   ms[2] the same kernel on the first step after a re-sort, reading each
+ *         particle through the re-sort order (it also writes the new order),
+ *   ms[3] number of those launches,
+ *   ms[4] far-mover kernel (particles beyond their tile's halo),
+ *   ms[5] Yee update, ms[6] re-sort (order computation and id permutation),
+ *   ms[7] total of the pic_step calls, ms[8] number of steps, ms[9] zero. */
+int pic_get_timers(pic_ctx* ctx, double ms[10]);
 
 /* Counters: out[0] far movers (particles that were outside their supercell's
  * LDS tile and took the global-memory path), out[1] re-sorts, out[2] steps,

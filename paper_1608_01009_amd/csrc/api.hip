@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/pic.h"
@@ -35,7 +36,8 @@ struct SpeciesState {
     bool loaded = false;
 };
 
-enum Stage { ST_PUSH = 0, ST_FDTD = 1, ST_SORT = 2, ST_TOTAL = 3, ST_N = 4 };
+enum Stage { ST_PUSH = 0, ST_PUSH_PERM = 1, ST_FAR = 2, ST_FDTD = 3, ST_SORT = 4, ST_TOTAL = 5,
+             ST_N = 6 };
 
 struct TimedRange {
     hipEvent_t a, b;
@@ -57,8 +59,10 @@ struct pic_ctx {
     Geom g{};
     int R = 1;
     std::vector<SpeciesState> sp;
-    double* E[3] = {};
+    double* E[3] = {};     // current fields
     double* B[3] = {};
+    double* Eo[3] = {};    // second pair: the Yee update writes here, then the pairs swap
+    double* Bo[3] = {};
     double* J[2][3] = {};
     int jcur = 0;     // J buffer holding the last step's current
     int jdep = 1;     // J buffer the next step deposits into (zero)
@@ -83,7 +87,8 @@ struct pic_ctx {
     int64_t rebins = 0;
     bool timers = false;
     double t_ms[ST_N] = {};
-    int64_t push_launches = 0;
+    int64_t push_launches = 0;       // push+deposit launches in stored order
+    int64_t push_perm_launches = 0;  // push+deposit launches reading through a re-sort order
     int64_t timed_steps = 0;
     std::vector<hipEvent_t> ev_free;
     std::vector<TimedRange> ranges;
@@ -317,6 +322,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     for (int d = 0; d < 3; ++d) {
         if ((e = dalloc(c, (void**)&c->E[d], fb)) != hipSuccess) return cfail(hip_fail(c, e, "hipMalloc E"));
         if ((e = dalloc(c, (void**)&c->B[d], fb)) != hipSuccess) return cfail(hip_fail(c, e, "hipMalloc B"));
+        if ((e = dalloc(c, (void**)&c->Eo[d], fb)) != hipSuccess) return cfail(hip_fail(c, e, "hipMalloc E"));
+        if ((e = dalloc(c, (void**)&c->Bo[d], fb)) != hipSuccess) return cfail(hip_fail(c, e, "hipMalloc B"));
         for (int b = 0; b < 2; ++b)
             if ((e = dalloc(c, (void**)&c->J[b][d], fb)) != hipSuccess)
                 return cfail(hip_fail(c, e, "hipMalloc J"));
@@ -486,31 +493,46 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
     }
     {
         Timed total(c, ST_TOTAL);
-        Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
         for (int it = 0; it < n_steps; ++it) {
+            const Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
+            const Fields fo{{c->Eo[0], c->Eo[1], c->Eo[2]}, {c->Bo[0], c->Bo[1], c->Bo[2]}};
             double* const* Jd = c->J[c->jdep];
             const bool sort_after = (c->steps_since_sort + 1 == c->R);
             for (auto& s : c->sp) {
                 if (s.n == 0) continue;
-                Timed t(c, ST_PUSH);
                 const Parts& src = s.buf[s.cur];
                 const Parts& dst = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
-                HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, s.pending ? s.perm : nullptr,
-                                              sort_after ? s.keys : nullptr, s.sc_off, f, Jd,
-                                              c->d_err, c->d_nfar, c->far_q,
-                                              c->far_n + c->far_phase,
-                                              c->far_n + (1 - c->far_phase), c->stream));
+                const unsigned* perm = s.pending ? s.perm : nullptr;
+                unsigned* keys = sort_after ? s.keys : nullptr;
+                unsigned* fn = c->far_n + c->far_phase;
+                unsigned* fn_next = c->far_n + (1 - c->far_phase);
+                {
+                    Timed t(c, s.pending ? ST_PUSH_PERM : ST_PUSH);
+                    HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, perm, keys, s.sc_off, f, Jd,
+                                                  c->d_err, c->d_nfar, c->far_q, fn, fn_next,
+                                                  c->stream));
+                }
+                {
+                    Timed t(c, ST_FAR);
+                    HIPCHK(c, launch_far_movers(c->g, s.c, src, dst, perm, keys, f, Jd, c->d_err,
+                                                c->d_nfar, c->far_q, fn, fn_next, c->stream));
+                }
                 c->far_phase = 1 - c->far_phase;
+                if (c->timers) (s.pending ? c->push_perm_launches : c->push_launches)++;
                 if (s.pending) {
+                    Timed t(c, ST_SORT);
                     HIPCHK(c, launch_permute_ids(s.n, s.perm, src.id, dst.id, c->stream));
                     s.cur = 1 - s.cur;
                     s.pending = false;
                 }
-                if (c->timers) c->push_launches++;
             }
             {
                 Timed t(c, ST_FDTD);
-                HIPCHK(c, launch_fdtd(c->g, f, Jd, c->J[c->jcur], c->stream));
+                HIPCHK(c, launch_fdtd(c->g, f, fo, Jd, c->J[c->jcur], c->stream));
+            }
+            for (int d = 0; d < 3; ++d) {
+                std::swap(c->E[d], c->Eo[d]);
+                std::swap(c->B[d], c->Bo[d]);
             }
             c->jcur = c->jdep;
             c->jdep = 1 - c->jdep;
@@ -642,22 +664,27 @@ int pic_enable_timers(pic_ctx* c, int32_t on) {
     c->timers = on != 0;
     for (int k = 0; k < ST_N; ++k) c->t_ms[k] = 0.0;
     c->push_launches = 0;
+    c->push_perm_launches = 0;
     c->timed_steps = 0;
     return PIC_OK;
 }
 
-int pic_get_timers(pic_ctx* c, double ms[6]) {
+int pic_get_timers(pic_ctx* c, double ms[10]) {
     if (!c) return PIC_EINVAL;
     c->err.clear();
     if (!ms) return fail(c, PIC_EINVAL, "ms must not be NULL");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     collect_timers(c);
     ms[0] = c->t_ms[ST_PUSH];
-    ms[1] = c->t_ms[ST_FDTD];
-    ms[2] = c->t_ms[ST_SORT];
-    ms[3] = c->t_ms[ST_TOTAL];
-    ms[4] = (double)c->push_launches;
-    ms[5] = (double)c->timed_steps;
+    ms[1] = (double)c->push_launches;
+    ms[2] = c->t_ms[ST_PUSH_PERM];
+    ms[3] = (double)c->push_perm_launches;
+    ms[4] = c->t_ms[ST_FAR];
+    ms[5] = c->t_ms[ST_FDTD];
+    ms[6] = c->t_ms[ST_SORT];
+    ms[7] = c->t_ms[ST_TOTAL];
+    ms[8] = (double)c->timed_steps;
+    ms[9] = 0.0;
     return PIC_OK;
 }
 

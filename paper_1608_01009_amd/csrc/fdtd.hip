@@ -1,10 +1,14 @@
 // Maxwell integration on the Yee lattice (stage 1 of the PIC step of
 // arXiv:1608.01009, Section 2), with B kept at integer time levels:
-//   B <- B - dt/2 curl E;  E <- E + dt (curl B - J);  B <- B - dt/2 curl E.
-// Three stencil passes over the periodic grid (each reads the neighbours the
-// previous pass wrote).  The E pass also clears the J buffer that the next
-// step deposits into.  The stencils are written in the order of the textbook
-// differences with contraction off, so E and B are reproducible bit for bit
+//   B' = B - dt/2 curl E;  E' = E + dt (curl B' - J);  B'' = B' - dt/2 curl E'.
+// One fused kernel: each workgroup owns a block of 8^3 cells and stages E
+// (block plus a halo of one below and two above), B (one below and one
+// above) and J in LDS, computes B' on the block plus halo, E' on the block
+// plus one layer above, then B'' on the block, and writes E' and B'' to a
+// second pair of arrays (the update is out of place, so neighbouring blocks
+// read only the old values).  It also clears the J buffer that the next step
+// deposits into.  The differences are written in the order of the textbook
+// stencils with contraction off, so E and B are reproducible bit for bit
 // given the same J.
 #include "pic_internal.h"
 
@@ -15,55 +19,169 @@ constexpr int kBlock = 256;
 
 struct FArgs {
     int n[3];
-    int ncell;
+    int nb[3];          // blocks per dimension
     double dt, hdt;
     double dx[3];
-    double* E[3];
-    double* B[3];
+    const double* E[3];
+    const double* B[3];
     const double* J[3];
+    double* Eo[3];
+    double* Bo[3];
     double* Jc[3];
 };
 
-__global__ void __launch_bounds__(kBlock) half_b_kernel(const FArgs a) {
-#pragma clang fp contract(off)
-    const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    for (int c = blockIdx.x * kBlock + threadIdx.x; c < a.ncell; c += gridDim.x * kBlock) {
-        const int i = c % nx;
-        const int jk = c / nx;
-        const int j = jk % ny, k = jk / ny;
-        const int ip = (i + 1 == nx) ? c - i : c + 1;
-        const int jp = (j + 1 == ny) ? c - j * nx : c + nx;
-        const int kp = (k + 1 == nz) ? c - k * nx * ny : c + nx * ny;
-        const double ex = a.E[0][c], ey = a.E[1][c], ez = a.E[2][c];
-        const double cx = (a.E[2][jp] - ez) / a.dx[1] - (a.E[1][kp] - ey) / a.dx[2];
-        const double cy = (a.E[0][kp] - ex) / a.dx[2] - (a.E[2][ip] - ez) / a.dx[0];
-        const double cz = (a.E[1][ip] - ey) / a.dx[0] - (a.E[0][jp] - ex) / a.dx[1];
-        a.B[0][c] = a.B[0][c] - a.hdt * cx;
-        a.B[1][c] = a.B[1][c] - a.hdt * cy;
-        a.B[2][c] = a.B[2][c] - a.hdt * cz;
+constexpr int YB = 8;                 // block edge in cells
+constexpr int YT = 512;               // threads per workgroup
+constexpr int NE = YB + 3;            // E tile edge: cells lo-1 .. hi+1
+constexpr int NBt = YB + 2;           // B tile edge: cells lo-1 .. hi
+constexpr int NE1 = YB + 1;           // E' tile edge: cells lo .. hi
+
+// i mod n; the tile coordinates lie in [-n, 2n) when n >= 3 (`near`)
+__device__ __forceinline__ int pwrap(int i, int n, bool near) {
+    if (near) {
+        i = i < 0 ? i + n : i;
+        return i >= n ? i - n : i;
     }
+    int r = i % n;
+    return r < 0 ? r + n : r;
 }
 
-__global__ void __launch_bounds__(kBlock) full_e_kernel(const FArgs a) {
+// UNIT: every dx_d == 1, where the divisions by dx_d are the identity and
+// are left out (the results are the same bit for bit).
+template <bool UNIT>
+__device__ __forceinline__ double ddx(double v, double dx) {
 #pragma clang fp contract(off)
+    return UNIT ? v : v / dx;
+}
+
+template <bool UNIT>
+__global__ void __launch_bounds__(YT) yee_kernel(const FArgs a) {
+#pragma clang fp contract(off)
+    __shared__ double e0[3][NE * NE * NE];
+    __shared__ double bt[3][NBt * NBt * NBt];
+    __shared__ double e1[3][NE1 * NE1 * NE1];
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    for (int c = blockIdx.x * kBlock + threadIdx.x; c < a.ncell; c += gridDim.x * kBlock) {
-        const int i = c % nx;
-        const int jk = c / nx;
-        const int j = jk % ny, k = jk / ny;
-        const int im = (i == 0) ? c + nx - 1 : c - 1;
-        const int jm = (j == 0) ? c + (ny - 1) * nx : c - nx;
-        const int km = (k == 0) ? c + (nz - 1) * nx * ny : c - nx * ny;
-        const double bx = a.B[0][c], by = a.B[1][c], bz = a.B[2][c];
-        const double cx = (bz - a.B[2][jm]) / a.dx[1] - (by - a.B[1][km]) / a.dx[2];
-        const double cy = (bx - a.B[0][km]) / a.dx[2] - (bz - a.B[2][im]) / a.dx[0];
-        const double cz = (by - a.B[1][im]) / a.dx[0] - (bx - a.B[0][jm]) / a.dx[1];
-        a.E[0][c] = a.E[0][c] + a.dt * (cx - a.J[0][c]);
-        a.E[1][c] = a.E[1][c] + a.dt * (cy - a.J[1][c]);
-        a.E[2][c] = a.E[2][c] + a.dt * (cz - a.J[2][c]);
-        a.Jc[0][c] = 0.0;
-        a.Jc[1][c] = 0.0;
-        a.Jc[2][c] = 0.0;
+    const int b = blockIdx.x;
+    const int bxi = b % a.nb[0], byz = b / a.nb[0];
+    const int byi = byz % a.nb[1], bzi = byz / a.nb[1];
+    const int lo[3] = {bxi * YB, byi * YB, bzi * YB};
+    const double dx0 = a.dx[0], dx1 = a.dx[1], dx2 = a.dx[2];
+    // block coordinates reach at most 2 cells beyond [0, n) on either side
+    const bool near = nx >= YB + 2 && ny >= YB + 2 && nz >= YB + 2;
+    auto gidx = [&](int x, int y, int z) {
+        return pwrap(x, nx, near) + nx * (pwrap(y, ny, near) + ny * pwrap(z, nz, near));
+    };
+    // J at the E' points of this thread, fetched before the staging barrier
+    constexpr int NJ = (NE1 * NE1 * NE1 + YT - 1) / YT;
+    double jv[NJ][3];
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        const int t = threadIdx.x + k * YT;
+        if (t < NE1 * NE1 * NE1) {
+            const int tx = t % NE1, ty = (t / NE1) % NE1, tz = t / (NE1 * NE1);
+            const int g = gidx(lo[0] + tx, lo[1] + ty, lo[2] + tz);
+            jv[k][0] = a.J[0][g];
+            jv[k][1] = a.J[1][g];
+            jv[k][2] = a.J[2][g];
+        }
+    }
+    // stage E (origin lo-1, edge NE) and B (origin lo-1, edge NBt): all
+    // global loads are issued before the first LDS store
+    constexpr int KE = (NE * NE * NE + YT - 1) / YT;
+    constexpr int KB = (NBt * NBt * NBt + YT - 1) / YT;
+    double ev[KE][3], bv[KB][3];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+        const int t = threadIdx.x + k * YT;
+        if (t < NE * NE * NE) {
+            const int tx = t % NE, ty = (t / NE) % NE, tz = t / (NE * NE);
+            const int g = gidx(lo[0] - 1 + tx, lo[1] - 1 + ty, lo[2] - 1 + tz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ev[k][c] = a.E[c][g];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int t = threadIdx.x + k * YT;
+        if (t < NBt * NBt * NBt) {
+            const int tx = t % NBt, ty = (t / NBt) % NBt, tz = t / (NBt * NBt);
+            const int g = gidx(lo[0] - 1 + tx, lo[1] - 1 + ty, lo[2] - 1 + tz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bv[k][c] = a.B[c][g];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+        const int t = threadIdx.x + k * YT;
+        if (t < NE * NE * NE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e0[c][t] = ev[k][c];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int t = threadIdx.x + k * YT;
+        if (t < NBt * NBt * NBt) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bt[c][t] = bv[k][c];
+        }
+    }
+    __syncthreads();
+    // B' = B - dt/2 curl E on cells lo-1 .. hi (E tile index = B tile index
+    // with the same origin, E tile edge NE)
+    for (int t = threadIdx.x; t < NBt * NBt * NBt; t += YT) {
+        const int tx = t % NBt, ty = (t / NBt) % NBt, tz = t / (NBt * NBt);
+        const int e = tx + NE * (ty + NE * tz);
+        const double ex = e0[0][e], ey = e0[1][e], ez = e0[2][e];
+        const int ip = e + 1, jp = e + NE, kp = e + NE * NE;
+        const double cx = ddx<UNIT>(e0[2][jp] - ez, dx1) - ddx<UNIT>(e0[1][kp] - ey, dx2);
+        const double cy = ddx<UNIT>(e0[0][kp] - ex, dx2) - ddx<UNIT>(e0[2][ip] - ez, dx0);
+        const double cz = ddx<UNIT>(e0[1][ip] - ey, dx0) - ddx<UNIT>(e0[0][jp] - ex, dx1);
+        bt[0][t] = bt[0][t] - a.hdt * cx;
+        bt[1][t] = bt[1][t] - a.hdt * cy;
+        bt[2][t] = bt[2][t] - a.hdt * cz;
+    }
+    __syncthreads();
+    // E' = E + dt (curl B' - J) on cells lo .. hi
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        const int t = threadIdx.x + k * YT;
+        if (t >= NE1 * NE1 * NE1) break;
+        const int tx = t % NE1, ty = (t / NE1) % NE1, tz = t / (NE1 * NE1);
+        const int bb = (tx + 1) + NBt * ((ty + 1) + NBt * (tz + 1));
+        const int e = (tx + 1) + NE * ((ty + 1) + NE * (tz + 1));
+        const double bx = bt[0][bb], by = bt[1][bb], bz = bt[2][bb];
+        const int im = bb - 1, jm = bb - NBt, km = bb - NBt * NBt;
+        const double cx = ddx<UNIT>(bz - bt[2][jm], dx1) - ddx<UNIT>(by - bt[1][km], dx2);
+        const double cy = ddx<UNIT>(bx - bt[0][km], dx2) - ddx<UNIT>(bz - bt[2][im], dx0);
+        const double cz = ddx<UNIT>(by - bt[1][im], dx0) - ddx<UNIT>(bx - bt[0][jm], dx1);
+        e1[0][t] = e0[0][e] + a.dt * (cx - jv[k][0]);
+        e1[1][t] = e0[1][e] + a.dt * (cy - jv[k][1]);
+        e1[2][t] = e0[2][e] + a.dt * (cz - jv[k][2]);
+    }
+    __syncthreads();
+    // B'' = B' - dt/2 curl E' on the block; write E', B'', clear J
+    for (int t = threadIdx.x; t < YB * YB * YB; t += YT) {
+        const int tx = t % YB, ty = (t / YB) % YB, tz = t / (YB * YB);
+        const int cx_ = lo[0] + tx, cy_ = lo[1] + ty, cz_ = lo[2] + tz;
+        if (cx_ >= nx || cy_ >= ny || cz_ >= nz) continue;
+        const int g = cx_ + nx * (cy_ + ny * cz_);
+        const int e = tx + NE1 * (ty + NE1 * tz);
+        const int bb = (tx + 1) + NBt * ((ty + 1) + NBt * (tz + 1));
+        const double ex = e1[0][e], ey = e1[1][e], ez = e1[2][e];
+        const int ip = e + 1, jp = e + NE1, kp = e + NE1 * NE1;
+        const double cx = ddx<UNIT>(e1[2][jp] - ez, dx1) - ddx<UNIT>(e1[1][kp] - ey, dx2);
+        const double cy = ddx<UNIT>(e1[0][kp] - ex, dx2) - ddx<UNIT>(e1[2][ip] - ez, dx0);
+        const double cz = ddx<UNIT>(e1[1][ip] - ey, dx0) - ddx<UNIT>(e1[0][jp] - ex, dx1);
+        a.Bo[0][g] = bt[0][bb] - a.hdt * cx;
+        a.Bo[1][g] = bt[1][bb] - a.hdt * cy;
+        a.Bo[2][g] = bt[2][bb] - a.hdt * cz;
+        a.Eo[0][g] = ex;
+        a.Eo[1][g] = ey;
+        a.Eo[2][g] = ez;
+        a.Jc[0][g] = 0.0;
+        a.Jc[1][g] = 0.0;
+        a.Jc[2][g] = 0.0;
     }
 }
 
@@ -81,24 +199,27 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_fdtd(const Geom& g, const Fields& f, double* const J[3],
+hipError_t launch_fdtd(const Geom& g, const Fields& f, const Fields& fo, double* const J[3],
                        double* const Jclear[3], hipStream_t s) {
     FArgs a;
     for (int d = 0; d < 3; ++d) {
         a.n[d] = g.n[d];
+        a.nb[d] = (g.n[d] + YB - 1) / YB;
         a.dx[d] = g.dx[d];
         a.E[d] = f.E[d];
         a.B[d] = f.B[d];
+        a.Eo[d] = fo.E[d];
+        a.Bo[d] = fo.B[d];
         a.J[d] = J[d];
         a.Jc[d] = Jclear[d];
     }
-    a.ncell = g.ncell;
     a.dt = g.dt;
     a.hdt = 0.5 * g.dt;
-    const int nb = grid_for(g.ncell);
-    hipLaunchKernelGGL(half_b_kernel, dim3(nb), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(full_e_kernel, dim3(nb), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(half_b_kernel, dim3(nb), dim3(kBlock), 0, s, a);
+    const int nb = a.nb[0] * a.nb[1] * a.nb[2];
+    if (g.dx[0] == 1.0 && g.dx[1] == 1.0 && g.dx[2] == 1.0)
+        hipLaunchKernelGGL(yee_kernel<true>, dim3(nb), dim3(YT), 0, s, a);
+    else
+        hipLaunchKernelGGL(yee_kernel<false>, dim3(nb), dim3(YT), 0, s, a);
     return hipGetLastError();
 }
 

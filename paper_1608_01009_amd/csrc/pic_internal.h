@@ -57,19 +57,28 @@ struct Fields {
 // previous species of this step, or zero).  Particle i of the new order is
 // read from src at perm[i] (or at i when perm is NULL) and written to dst at
 // i (dst may equal src when perm is NULL).  keys, when not NULL, receives the
-// sort key of every particle's new position.  far_q (capacity >= particles)
-// and the counters far_n (zero on entry) / far_n_next (cleared here for the
-// next launch) carry the particles outside their tile to a second kernel.
+// sort key of every particle's new position.  Particles outside their
+// supercell's tile are appended to far_q (capacity >= particles; counter
+// far_n, zero on entry) and left to launch_far_movers, which must follow
+// with the same arguments.
 hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& src,
                                const Parts& dst, const unsigned* perm, unsigned* keys,
                                const int* sc_off, const Fields& f, double* const J[3],
                                unsigned* err, unsigned long long* nfar, int* far_q,
                                unsigned* far_n, unsigned* far_n_next, hipStream_t s);
+// The particles queued by launch_push_deposit, through global memory; clears
+// far_n_next (the counter of the next launch).
+hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src,
+                             const Parts& dst, const unsigned* perm, unsigned* keys,
+                             const Fields& f, double* const J[3], unsigned* err,
+                             unsigned long long* nfar, int* far_q, unsigned* far_n,
+                             unsigned* far_n_next, hipStream_t s);
 int push_deposit_lds_bytes(const Geom& g);
 bool push_deposit_supported(int S, int h);
 
-// Yee update; also clears Jclear (the buffer the next step deposits into).
-hipError_t launch_fdtd(const Geom& g, const Fields& f, double* const J[3],
+// Yee update from the fields f into fo (distinct arrays); also clears Jclear
+// (the buffer the next step deposits into).
+hipError_t launch_fdtd(const Geom& g, const Fields& f, const Fields& fo, double* const J[3],
                        double* const Jclear[3], hipStream_t s);
 
 // Fill n doubles with zero.

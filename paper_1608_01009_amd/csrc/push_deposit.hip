@@ -787,7 +787,6 @@ hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
     else
         hipLaunchKernelGGL((push_deposit_kernel<S, H, false>), dim3(args.g.nsc), dim3(kBlock), 0,
                            s, args);
-    hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
 
@@ -819,11 +818,12 @@ int push_deposit_lds_bytes(const Geom& g) {
     return -1;
 }
 
-hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& src,
-                               const Parts& dst, const unsigned* perm, unsigned* keys,
-                               const int* sc_off, const Fields& f, double* const J[3],
-                               unsigned* err, unsigned long long* nfar, int* far_q,
-                               unsigned* far_n, unsigned* far_n_next, hipStream_t s) {
+namespace {
+
+PDArgs make_args(const Geom& g, const SpeciesC& sp, const Parts& src, const Parts& dst,
+                 const unsigned* perm, unsigned* keys, const int* sc_off, const Fields& f,
+                 double* const J[3], unsigned* err, unsigned long long* nfar, int* far_q,
+                 unsigned* far_n, unsigned* far_n_next) {
     PDArgs args;
     args.g = g;
     args.sp = sp;
@@ -842,11 +842,34 @@ hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& s
     args.far_q = far_q;
     args.far_n = far_n;
     args.far_n_next = far_n_next;
+    return args;
+}
+
+}  // namespace
+
+hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& src,
+                               const Parts& dst, const unsigned* perm, unsigned* keys,
+                               const int* sc_off, const Fields& f, double* const J[3],
+                               unsigned* err, unsigned long long* nfar, int* far_q,
+                               unsigned* far_n, unsigned* far_n_next, hipStream_t s) {
+    const PDArgs args = make_args(g, sp, src, dst, perm, keys, sc_off, f, J, err, nfar, far_q,
+                                  far_n, far_n_next);
     if (g.nsc <= 0) return hipSuccess;
 #define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return launch_sh<s_, h_>(args, s);
     PIC_SH_TABLE(PIC_X)
 #undef PIC_X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src,
+                             const Parts& dst, const unsigned* perm, unsigned* keys,
+                             const Fields& f, double* const J[3], unsigned* err,
+                             unsigned long long* nfar, int* far_q, unsigned* far_n,
+                             unsigned* far_n_next, hipStream_t s) {
+    const PDArgs args = make_args(g, sp, src, dst, perm, keys, nullptr, f, J, err, nfar, far_q,
+                                  far_n, far_n_next);
+    hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
+    return hipGetLastError();
 }
 
 }  // namespace pic

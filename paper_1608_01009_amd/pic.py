@@ -211,7 +211,10 @@ def pic_enable_timers(ctx, on: bool = True):
 
 
 def pic_get_timers(ctx) -> np.ndarray:
-    out = np.zeros(6)
+    """ms[0] push+deposit in stored order, ms[1] its launches, ms[2] push+deposit
+    through a re-sort order, ms[3] its launches, ms[4] far movers, ms[5] Yee
+    update, ms[6] re-sort, ms[7] total, ms[8] steps, ms[9] zero."""
+    out = np.zeros(10)
     _check(ctx, library().pic_get_timers(ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
 
