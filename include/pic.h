@@ -122,8 +122,11 @@ int pic_get_particles(pic_ctx* ctx, int32_t species, int64_t capacity, int64_t* 
 int pic_diagnostics(pic_ctx* ctx, double out[8]);
 
 /* Stage timers (HIP events on the context stream), off by default.
- * pic_enable_timers(ctx, 1) turns them on and resets them. */
-int pic_enable_timers(pic_ctx* ctx, int32_t on);
+ * pic_enable_timers(ctx, mode) resets them and sets the mode: 0 off, 1 every
+ * stage below, 2 only the push+deposit kernel in stored order (ms[0]; one
+ * event pair per step, which keeps the timing overhead out of the other
+ * stages).  Other modes: PIC_EINVAL. */
+int pic_enable_timers(pic_ctx* ctx, int32_t mode);
 
 /* Milliseconds summed over the timed steps, and launch counts:
  *   ms[0] push+deposit kernel (gather, Boris, advance, VB deposit into the

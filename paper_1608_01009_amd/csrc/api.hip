@@ -85,7 +85,7 @@ struct pic_ctx {
     int64_t steps = 0;
     int steps_since_sort = 0;
     int64_t rebins = 0;
-    bool timers = false;
+    int timers = 0;        // 0 off, 1 every stage, 2 the stored-order push+deposit kernel only
     double t_ms[ST_N] = {};
     int64_t push_launches = 0;       // push+deposit launches in stored order
     int64_t push_perm_launches = 0;  // push+deposit launches reading through a re-sort order
@@ -156,7 +156,7 @@ struct Timed {
     int stage;
     hipEvent_t a = nullptr;
     Timed(pic_ctx* c_, int st) : c(c_), stage(st) {
-        if (c->timers) {
+        if (c->timers == 1 || (c->timers == 2 && st == ST_PUSH)) {
             a = take_event(c);
             if (a) (void)hipEventRecord(a, c->stream);
         }
@@ -661,7 +661,8 @@ int pic_enable_timers(pic_ctx* c, int32_t on) {
     c->err.clear();
     (void)hipStreamSynchronize(c->stream);
     collect_timers(c);
-    c->timers = on != 0;
+    if (on < 0 || on > 2) return fail(c, PIC_EINVAL, "timer mode must be 0, 1 or 2");
+    c->timers = on;
     for (int k = 0; k < ST_N; ++k) c->t_ms[k] = 0.0;
     c->push_launches = 0;
     c->push_perm_launches = 0;

@@ -206,8 +206,9 @@ def pic_diagnostics(ctx) -> np.ndarray:
     return out
 
 
-def pic_enable_timers(ctx, on: bool = True):
-    _check(ctx, library().pic_enable_timers(ctx, 1 if on else 0))
+def pic_enable_timers(ctx, on=True):
+    """on: False/0 off, True/1 every stage, 2 the stored-order push+deposit only."""
+    _check(ctx, library().pic_enable_timers(ctx, int(on)))
 
 
 def pic_get_timers(ctx) -> np.ndarray:

@@ -148,6 +148,15 @@ def test_timers_and_counters():
     assert c[1] == 1 and c[2] == 25
     # E/B tile 8^3 x 6, padded J tile 3 x 1001, crosser queues 8 waves x 6 x 28 doubles
     assert c[3] == (6 * 544 + 3 * 1001 + 8 * 6 * 28) * 8    # E/B tile, J tile, crosser queues
+    # mode 2: only the stored-order push+deposit kernel is bracketed
+    pic.pic_enable_timers(sim.ctx, 2)
+    sim.step(5)
+    t = pic.pic_get_timers(sim.ctx)
+    assert t[0] > 0 and t[1] == 5 and t[8] == 5
+    assert t[2] == 0 and t[4] == 0 and t[5] == 0 and t[6] == 0 and t[7] == 0
+    with pytest.raises(pic.PicError) as ei:
+        pic.pic_enable_timers(sim.ctx, 3)
+    assert ei.value.code == pic.PIC_EINVAL
     sim.close()
 
 
