@@ -1,4 +1,5 @@
-"""CPU FP64 oracle of the PIC step -- TEST INFRASTRUCTURE, not product code.
+"""CPU FP64 oracle of the PIC step (and of its mixed-precision variant) --
+TEST INFRASTRUCTURE, not product code.
 
 Thin ctypes wrapper around ``liborc.so`` (built from ``pic_oracle.c``).  Only
 the test suite, the smoke check and the benchmark's CPU-baseline leg may
@@ -56,6 +57,11 @@ def lib():
         L.orc_rebin.argtypes = [G, C.c_int64, _D, _D, _D, _D, _D, _D, _I64]
         L.orc_push_deposit.argtypes = [G, C.c_double, C.c_double, C.c_double, C.c_int64,
                                        _D, _D, _D, _D, _D, _D, PP6, PP3]
+        L.orc_mixed_round_pos.argtypes = [C.c_double, C.c_int64]
+        L.orc_mixed_round_pos.restype = C.c_double
+        L.orc_push_deposit_mixed.argtypes = [G, C.c_double, C.c_double, C.c_double, C.c_int64,
+                                             _D, _D, _D, _D, _D, _D, PP6, PP3, C.c_void_p,
+                                             C.c_void_p]
         L.orc_rho.argtypes = [G, C.c_double, C.c_double, C.c_int64, _D, _D, _D, _D]
         L.orc_gauss.argtypes = [G, PP3, _D, _D]
         L.orc_divb.argtypes = [G, PP3, _D]
@@ -158,6 +164,26 @@ def divb(g: OrcGrid, B):
     return out
 
 
+def mixed_round_pos(x, n):
+    """Positions as the mixed-precision variant stores them (integer cell +
+    FP32 offset), as FP64 values."""
+    f = lib().orc_mixed_round_pos
+    x = np.asarray(x, dtype=np.float64)
+    return np.array([f(float(v), int(n)) for v in x.ravel()]).reshape(x.shape)
+
+
+def push_deposit_mixed(g: OrcGrid, q, m, w, x, y, z, ux, uy, uz, EB, J, Jabs=None, Jcnt=None):
+    """Mixed-precision particle loop (in place on the six FP64 arrays, which
+    must hold values of the variant); J, Jabs (FP64) and Jcnt (int64) are
+    lists of three flat arrays or None."""
+    ja = _ptrs(Jabs) if Jabs is not None else None
+    jn = (_I64 * 3)(*[_ip(a) for a in Jcnt]) if Jcnt is not None else None
+    lib().orc_push_deposit_mixed(C.byref(g), q, m, w, len(x), _dp(x), _dp(y), _dp(z), _dp(ux),
+                                 _dp(uy), _dp(uz), _ptrs(EB), _ptrs(J),
+                                 C.cast(ja, C.c_void_p) if ja is not None else None,
+                                 C.cast(jn, C.c_void_p) if jn is not None else None)
+
+
 # ---- whole-state simulator -------------------------------------------------
 
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz")
@@ -170,7 +196,9 @@ class OracleSim:
     cell units.  Field arrays are flat, x-fastest, ``n[0]*n[1]*n[2]`` long.
     """
 
-    def __init__(self, n, dx, dt, species, S=4, R=20):
+    def __init__(self, n, dx, dt, species, S=4, R=20, precision="fp64"):
+        assert precision in ("fp64", "mixed")
+        self.precision = precision
         self.n = tuple(int(v) for v in n)
         self.dx = tuple(float(v) for v in dx)
         self.dt = float(dt)
@@ -190,6 +218,8 @@ class OracleSim:
 
     def load_particles(self, s, x, y, z, ux, uy, uz, ids=None):
         arrs = [np.array(a, dtype=np.float64).ravel() for a in (x, y, z, ux, uy, uz)]
+        if self.precision == "mixed":
+            arrs = self.to_mixed(arrs)
         n = len(arrs[0])
         ids = np.arange(n, dtype=np.int64) if ids is None else np.array(ids, dtype=np.int64)
         self.P[s] = arrs + [ids]
@@ -207,6 +237,11 @@ class OracleSim:
         for c in range(6):
             self.F[c] = np.array(EB[c], dtype=np.float64).ravel().copy()
         self.steps_since_sort = int(steps_since_sort)
+
+    def to_mixed(self, arrs):
+        """x, y, z, ux, uy, uz as the mixed-precision variant stores them."""
+        out = [mixed_round_pos(arrs[d], self.n[d]) for d in range(3)]
+        return out + [np.asarray(a, dtype=np.float32).astype(np.float64) for a in arrs[3:6]]
 
     def _sort(self, s):
         x, y, z, ux, uy, uz, ids = self.P[s]
@@ -230,8 +265,13 @@ class OracleSim:
                 if self.P[s] is None or len(self.P[s][0]) == 0:
                     continue
                 x, y, z, ux, uy, uz, _ = self.P[s]
-                L.orc_push_deposit(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y), _dp(z),
-                                   _dp(ux), _dp(uy), _dp(uz), EB, J)
+                if self.precision == "mixed":
+                    L.orc_push_deposit_mixed(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y),
+                                             _dp(z), _dp(ux), _dp(uy), _dp(uz), EB, J, None,
+                                             None)
+                else:
+                    L.orc_push_deposit(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y), _dp(z),
+                                       _dp(ux), _dp(uy), _dp(uz), EB, J)
             L.orc_fdtd(C.byref(self.g), _ptrs(self.F[0:3]), _ptrs(self.F[3:6]),
                        _ptrs(self.F[6:9]))
             self.step_count += 1

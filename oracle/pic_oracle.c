@@ -458,3 +458,234 @@ double orc_field_energy(const orc_grid* g, const double* const F[], int ncomp) {
         for (int64_t i = 0; i < nc; ++i) s += F[c][i] * F[c][i];
     return 0.5 * s * dv;
 }
+
+/* ---------------------------------------------------------------------------
+ * Mixed-precision variant of the particle loop (an extension beyond the
+ * paper, which computes in double precision throughout, Section 3).
+ *
+ * A position is stored as an integer cell c_d and an FP32 offset o_d in
+ * [0, 1) (x_d = c_d + o_d exactly), the momentum as three FP32 values.  The
+ * step performs the FP64 scheme's operations in FP32 arithmetic (every
+ * operation rounded to single precision; fused multiply-adds where the FP64
+ * scheme has them), with cell-local coordinates:
+ *   gather:  per component and axis with stagger 1/2: i = c, f = o - 1/2 if
+ *            o >= 1/2, else i = c - 1, f = o + 1/2; stagger 0: i = c, f = o;
+ *            field values rounded to FP32, nested lerps x, y, z;
+ *   Boris:   as orc_boris with h = (float)(q dt / 2m);
+ *   advance: o* = fma((float)(dt/dx_d) u_d, g, o) with g = 1/sqrt(1+|u|^2),
+ *            relative to the cell corner (so o* lies in (-1, 2));
+ *   deposit: the VB split and segment weights of orc_deposit_vb in FP32 in
+ *            cell-local coordinates, jc_d = (float)(q w / (dt area_d)); each
+ *            segment contribution is added to the FP64 J;
+ *   cell:    s = floor(o*), c = (c + s) mod n, o = o* - s; an offset that
+ *            rounds to 1 becomes 0 in the next cell.
+ * The fields, the Yee update and J stay FP64.  Jabs and Jcnt (optional)
+ * receive the sum of |contribution| and the number of contributions per J
+ * node, which bound the effect of summing the FP32 contributions in another
+ * order or precision.
+ * ------------------------------------------------------------------------- */
+static float lerpf_(float a, float b, float f) { return fmaf(f, b - a, a); }
+
+/* cell and FP32 offset of a position x in [0, n): x - c is exact in FP64 */
+static void split_pos(double x, int64_t n, int64_t* c, float* o) {
+    double fl = floor(x);
+    int64_t ci = (int64_t)fl;
+    float of = (float)(x - fl);
+    if (of >= 1.0f) {
+        of = 0.0f;
+        ci = ci + 1 == n ? 0 : ci + 1;
+    }
+    *c = ci;
+    *o = of;
+}
+
+double orc_mixed_round_pos(double x, int64_t n) {
+    int64_t c;
+    float o;
+    split_pos(x, n, &c, &o);
+    return (double)c + (double)o;
+}
+
+static void gather_mixed(const orc_grid* g, const double* const EB[6], const int64_t c[3],
+                         const float o[3], float out[6]) {
+    for (int comp = 0; comp < 6; ++comp) {
+        int64_t i[3];
+        float f[3];
+        for (int d = 0; d < 3; ++d) {
+            if (STAG[comp][d] != 0.0) {
+                if (o[d] >= 0.5f) {
+                    i[d] = c[d];
+                    f[d] = o[d] - 0.5f;
+                } else {
+                    i[d] = c[d] - 1;
+                    f[d] = o[d] + 0.5f;
+                }
+            } else {
+                i[d] = c[d];
+                f[d] = o[d];
+            }
+        }
+        float fz[2];
+        for (int cc = 0; cc < 2; ++cc) {
+            float fy[2];
+            for (int b = 0; b < 2; ++b) {
+                float f0 = (float)EB[comp][lin(g, i[0], i[1] + b, i[2] + cc)];
+                float f1 = (float)EB[comp][lin(g, i[0] + 1, i[1] + b, i[2] + cc)];
+                fy[b] = lerpf_(f0, f1, f[0]);
+            }
+            fz[cc] = lerpf_(fy[0], fy[1], f[1]);
+        }
+        out[comp] = lerpf_(fz[0], fz[1], f[2]);
+    }
+}
+
+static float one_plus_sqf(const float v[3]) {
+    return fmaf(v[2], v[2], fmaf(v[1], v[1], fmaf(v[0], v[0], 1.0f)));
+}
+
+static float add_crossf(const float a[3], const float b[3], const float c[3], int d) {
+    const int e = (d + 1) % 3, f = (d + 2) % 3;
+    return fmaf(b[e], c[f], fmaf(-b[f], c[e], a[d]));
+}
+
+static void boris_mixed(float h, const float EB[6], float u[3]) {
+    const float* E = EB;
+    const float* B = EB + 3;
+    float um[3], t[3], s[3], up[3], upl[3];
+    for (int d = 0; d < 3; ++d) um[d] = fmaf(h, E[d], u[d]);
+    float gm = sqrtf(one_plus_sqf(um));
+    float hg = h / gm;
+    for (int d = 0; d < 3; ++d) t[d] = hg * B[d];
+    float sf = 2.0f / one_plus_sqf(t);
+    for (int d = 0; d < 3; ++d) s[d] = sf * t[d];
+    for (int d = 0; d < 3; ++d) up[d] = add_crossf(um, um, t, d);
+    for (int d = 0; d < 3; ++d) upl[d] = add_crossf(um, up, s, d);
+    for (int d = 0; d < 3; ++d) u[d] = fmaf(h, E[d], upl[d]);
+}
+
+static void add_j(const orc_grid* g, double* const J[3], double* const* Jabs, int64_t* const* Jcnt,
+                  int d, int64_t i, int64_t j, int64_t k, float v) {
+    int64_t n = lin(g, i, j, k);
+    J[d][n] += (double)v;
+    if (Jabs) Jabs[d][n] += fabs((double)v);
+    if (Jcnt) Jcnt[d][n] += 1;
+}
+
+/* one segment A -> B (cell-local coordinates relative to the start cell's
+ * corner) inside the cell with relative corner rc; cell = start cell */
+static void vb_segment_mixed(const orc_grid* g, double* const J[3], double* const* Jabs,
+                             int64_t* const* Jcnt, const int64_t cell[3], const int rc[3],
+                             const float A[3], const float B[3], const float jc[3]) {
+    float a[3], b[3], dl[3], m[3];
+    for (int d = 0; d < 3; ++d) {
+        a[d] = A[d] - (float)rc[d];
+        b[d] = B[d] - (float)rc[d];
+        dl[d] = b[d] - a[d];
+        m[d] = 0.5f * (a[d] + b[d]);
+    }
+    for (int d = 0; d < 3; ++d) {
+        int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+        int p = e1 < e2 ? e1 : e2;
+        int r = e1 < e2 ? e2 : e1;
+        float cross = (dl[p] * dl[r]) / 12.0f;
+        float flux = jc[d] * dl[d];
+        for (int bp = 0; bp < 2; ++bp) {
+            float wp = bp ? m[p] : 1.0f - m[p];
+            for (int br = 0; br < 2; ++br) {
+                float wr = br ? m[r] : 1.0f - m[r];
+                float W = wp * wr + ((bp == br) ? cross : -cross);
+                int64_t idx[3] = {cell[0] + rc[0], cell[1] + rc[1], cell[2] + rc[2]};
+                idx[p] += bp;
+                idx[r] += br;
+                add_j(g, J, Jabs, Jcnt, d, idx[0], idx[1], idx[2], flux * W);
+            }
+        }
+    }
+}
+
+static void deposit_mixed(const orc_grid* g, double* const J[3], double* const* Jabs,
+                          int64_t* const* Jcnt, const int64_t cell[3], const float o0[3],
+                          const float o1[3], const float jc[3]) {
+    float dv[3];
+    int c1[3];
+    for (int d = 0; d < 3; ++d) {
+        dv[d] = o1[d] - o0[d];
+        c1[d] = (int)floorf(o1[d]);
+    }
+    int nc = 0;
+    float tc[3], pc[3];
+    int dc[3];
+    for (int d = 0; d < 3; ++d) {
+        if (c1[d] != 0) {
+            float p = (float)(c1[d] > 0 ? c1[d] : 0);
+            tc[nc] = (p - o0[d]) / dv[d];
+            pc[nc] = p;
+            dc[nc] = d;
+            ++nc;
+        }
+    }
+    for (int i = 1; i < nc; ++i) {
+        int j = i;
+        while (j > 0 && tc[j - 1] > tc[j]) {
+            float tt = tc[j]; tc[j] = tc[j - 1]; tc[j - 1] = tt;
+            float pp = pc[j]; pc[j] = pc[j - 1]; pc[j - 1] = pp;
+            int dd = dc[j]; dc[j] = dc[j - 1]; dc[j - 1] = dd;
+            --j;
+        }
+    }
+    float A[3] = {o0[0], o0[1], o0[2]};
+    int rc[3] = {0, 0, 0};
+    for (int k = 0; k <= nc; ++k) {
+        float B[3];
+        if (k < nc) {
+            for (int d = 0; d < 3; ++d) B[d] = fmaf(tc[k], dv[d], o0[d]);
+            B[dc[k]] = pc[k];
+        } else {
+            for (int d = 0; d < 3; ++d) B[d] = o1[d];
+        }
+        vb_segment_mixed(g, J, Jabs, Jcnt, cell, rc, A, B, jc);
+        if (k < nc) {
+            for (int d = 0; d < 3; ++d) A[d] = B[d];
+            rc[dc[k]] = c1[dc[k]];
+        }
+    }
+}
+
+void orc_push_deposit_mixed(const orc_grid* g, double q, double m, double w, int64_t n,
+                            double* x, double* y, double* z, double* ux, double* uy,
+                            double* uz, const double* const EB[6], double* const J[3],
+                            double* const* Jabs, int64_t* const* Jcnt) {
+    const float h = (float)((q * g->dt) / (2.0 * m));
+    float cdt[3], jc[3];
+    for (int d = 0; d < 3; ++d) {
+        cdt[d] = (float)(g->dt / g->dx[d]);
+        double area = g->dx[(d + 1) % 3] * g->dx[(d + 2) % 3];
+        jc[d] = (float)((q * w) / (g->dt * area));
+    }
+    double* X[3] = {x, y, z};
+    double* U[3] = {ux, uy, uz};
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t c[3];
+        float o[3], u[3], f[6], o1[3];
+        for (int d = 0; d < 3; ++d) {
+            split_pos(X[d][p], g->n[d], &c[d], &o[d]);
+            u[d] = (float)U[d][p];
+        }
+        gather_mixed(g, EB, c, o, f);
+        boris_mixed(h, f, u);
+        float gi = 1.0f / sqrtf(one_plus_sqf(u));
+        for (int d = 0; d < 3; ++d) o1[d] = fmaf(cdt[d] * u[d], gi, o[d]);
+        deposit_mixed(g, J, Jabs, Jcnt, c, o, o1, jc);
+        for (int d = 0; d < 3; ++d) {
+            float s = floorf(o1[d]);
+            int64_t cn = wrapi(c[d] + (int64_t)s, g->n[d]);
+            float on = o1[d] - s;
+            if (on >= 1.0f) {
+                on = 0.0f;
+                cn = cn + 1 == g->n[d] ? 0 : cn + 1;
+            }
+            X[d][p] = (double)cn + (double)on;
+            U[d][p] = (double)u[d];
+        }
+    }
+}

@@ -76,6 +76,20 @@ void orc_push_deposit(const orc_grid* g, double q, double m, double w,
                       double* ux, double* uy, double* uz,
                       const double* const EB[6], double* const J[3]);
 
+/* Mixed-precision variant (integer cell + FP32 offset and FP32 momentum;
+ * fields and J FP64).  orc_mixed_round_pos: the position x in [0, n) as
+ * stored by the variant (cell + offset rounded to FP32, exactly
+ * representable in FP64).  orc_push_deposit_mixed: the particle loop of one
+ * species in that arithmetic; positions and momenta are passed as FP64
+ * arrays holding values of the variant (as orc_mixed_round_pos and FP32
+ * momenta give).  Jabs / Jcnt, when not NULL, accumulate the absolute value
+ * and the number of contributions per J node. */
+double orc_mixed_round_pos(double x, int64_t n);
+void orc_push_deposit_mixed(const orc_grid* g, double q, double m, double w, int64_t n,
+                            double* x, double* y, double* z, double* ux, double* uy,
+                            double* uz, const double* const EB[6], double* const J[3],
+                            double* const* Jabs, int64_t* const* Jcnt);
+
 /* CIC charge density at the nodes: rho += q w W(x-i)W(y-j)W(z-k) / dV. */
 void orc_rho(const orc_grid* g, double q, double w, int64_t n,
              const double* x, const double* y, const double* z, double* rho);
