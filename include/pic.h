@@ -59,13 +59,25 @@ typedef enum {
     PIC_ESTATE = -6       /* call order violated (e.g. step before any load) */
 } pic_status;
 
+/* Arithmetic of the particle loop (gather, push, deposit). */
+enum {
+    PIC_FP64 = 0,        /* double precision throughout (Section 3 of the paper) */
+    PIC_FP32_MIXED = 1   /* positions as integer cell + FP32 offset in [0, 1), FP32 momenta,
+                            FP32 gather / Boris / VB split and weights in cell-local
+                            coordinates, FP32 LDS J tiles summed into the FP64 J; fields,
+                            Yee update and J stay FP64.  Loaded positions are rounded to
+                            that form, loaded momenta to FP32; pic_get_particles returns
+                            cell + offset exactly.  At most 1024 cells per dimension. */
+};
+
 typedef struct {
     int32_t n[3];           /* cells per dimension; each a multiple of `supercell` */
     int32_t supercell;      /* S: supercell edge in cells (Section 4.3); 1..6 with halo 1,
                                1, 2 or 4 with halo 2 */
     int32_t rebin_every;    /* R >= 1: stable re-sort after every R-th step since the last sort */
     int32_t halo;           /* h: drift margin in cells of the per-supercell LDS tiles; 0 -> 1 */
-    int32_t reserved[4];    /* must be zero */
+    int32_t precision;      /* PIC_FP64 or PIC_FP32_MIXED */
+    int32_t reserved[3];    /* must be zero */
     void* stream;           /* hipStream_t to run on, or NULL for a library-owned stream */
 } pic_grid_t;
 
@@ -86,7 +98,8 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                const pic_species_t* species, int32_t n_species, pic_ctx** out);
 
 /* Replace the particles of one species with n particles (n <= capacity).
- * x, y, z in [0, n_d) and finite u are required (PIC_EINVAL otherwise).
+ * x, y, z in [0, n_d) and finite u are required (PIC_EINVAL otherwise; with
+ * PIC_FP32_MIXED also |u| within the FP32 range).
  * id may be NULL (ids 0..n-1).  The particles are re-sorted as described
  * above (their input order breaks ties) and the re-sort counter restarts. */
 int pic_load_particles(pic_ctx* ctx, int32_t species, int64_t n,

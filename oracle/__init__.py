@@ -211,6 +211,11 @@ class OracleSim:
         self.P = [None] * len(self.species)
         self.steps_since_sort = 0
         self.step_count = 0
+        # mixed precision only: when True, each step also records per J node
+        # the sum of |contribution| (Jabs) and the number of contributions (Jcnt)
+        self.collect_abs = False
+        self.Jabs = None
+        self.Jcnt = None
 
     @property
     def ncells(self):
@@ -261,14 +266,21 @@ class OracleSim:
                 self.F[c][:] = 0.0
             EB = _ptrs(self.F[:6])
             J = _ptrs(self.F[6:9])
+            ja = jn = None
+            if self.precision == "mixed" and self.collect_abs:
+                self.Jabs = [np.zeros(self.ncells) for _ in range(3)]
+                self.Jcnt = [np.zeros(self.ncells, dtype=np.int64) for _ in range(3)]
+                ja_arr = _ptrs(self.Jabs)                 # kept alive for the calls below
+                jn_arr = (_I64 * 3)(*[_ip(a) for a in self.Jcnt])
+                ja = C.cast(ja_arr, C.c_void_p)
+                jn = C.cast(jn_arr, C.c_void_p)
             for s, (q, m, w) in enumerate(self.species):
                 if self.P[s] is None or len(self.P[s][0]) == 0:
                     continue
                 x, y, z, ux, uy, uz, _ = self.P[s]
                 if self.precision == "mixed":
                     L.orc_push_deposit_mixed(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y),
-                                             _dp(z), _dp(ux), _dp(uy), _dp(uz), EB, J, None,
-                                             None)
+                                             _dp(z), _dp(ux), _dp(uy), _dp(uz), EB, J, ja, jn)
                 else:
                     L.orc_push_deposit(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y), _dp(z),
                                        _dp(ux), _dp(uy), _dp(uz), EB, J)

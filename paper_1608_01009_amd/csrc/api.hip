@@ -27,7 +27,9 @@ struct SpeciesState {
     SpeciesC c;
     int64_t capacity = 0;
     int64_t n = 0;
-    Parts buf[2] = {};
+    Parts buf[2] = {};         // FP64 arrays (PIC_FP64)
+    PartsM bufm[2] = {};       // packed arrays (PIC_FP32_MIXED)
+    SpeciesM cm{};             // FP32 constants of the mixed-precision push
     int cur = 0;               // buffer holding the particles
     int* sc_off = nullptr;     // supercell offsets of the (new) order
     unsigned* keys = nullptr;  // sort keys written by the push before a re-sort
@@ -54,6 +56,8 @@ __global__ void iota_kernel(int64_t* id, int64_t n) {
 
 struct pic_ctx {
     int device = 0;
+    int precision = PIC_FP64;
+    double* stage[6] = {};   // mixed precision: FP64 staging of x, y, z, ux, uy, uz
     hipStream_t stream = nullptr;
     bool own_stream = false;
     Geom g{};
@@ -200,13 +204,27 @@ int sync_and_check(pic_ctx* c, bool stepping) {
     return PIC_OK;
 }
 
+// FP64 positions and momenta of a species in stored order: the particle
+// arrays themselves, or (mixed precision) their conversion into the staging
+// arrays, valid until the next use of the staging arrays.
+hipError_t fp64_view(pic_ctx* c, const SpeciesState& s, Parts& v) {
+    if (c->precision == PIC_FP64) {
+        v = s.buf[s.cur];
+        return hipSuccess;
+    }
+    v = Parts{c->stage[0], c->stage[1], c->stage[2], c->stage[3], c->stage[4], c->stage[5],
+              s.bufm[s.cur].id};
+    return launch_to_double(s.n, s.bufm[s.cur], c->stage, c->stream);
+}
+
 int compute_refs(pic_ctx* c) {
     const int64_t nc = c->g.ncell;
     HIPCHK(c, launch_zero(c->rho, nc, c->stream));
     const double dv = c->g.dx[0] * c->g.dx[1] * c->g.dx[2];
     for (auto& s : c->sp) {
         if (s.n == 0) continue;
-        const Parts& p = s.buf[s.cur];
+        Parts p;
+        HIPCHK(c, fp64_view(c, s, p));
         HIPCHK(c, launch_rho(c->g, (s.c.q * s.c.w) / dv, p.x, p.y, p.z, s.n, c->rho, c->stream));
     }
     Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
@@ -228,7 +246,10 @@ int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys) {
 // Apply a pending re-sort order to the particle data (outside pic_step).
 int resolve_pending(pic_ctx* c, SpeciesState& s) {
     if (!s.pending) return PIC_OK;
-    HIPCHK(c, launch_permute(s.n, s.perm, s.buf[s.cur], s.buf[1 - s.cur], c->stream));
+    if (c->precision == PIC_FP64)
+        HIPCHK(c, launch_permute(s.n, s.perm, s.buf[s.cur], s.buf[1 - s.cur], c->stream));
+    else
+        HIPCHK(c, launch_permute_mixed(s.n, s.perm, s.bufm[s.cur], s.bufm[1 - s.cur], c->stream));
     s.cur = 1 - s.cur;
     s.pending = false;
     return PIC_OK;
@@ -250,8 +271,13 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     if (!grid || !dx) return bad("grid and dx must not be NULL");
     if (n_species < 1 || n_species > 64 || !species)
         return bad("n_species must be in [1, 64] with a species array");
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 3; ++r)
         if (grid->reserved[r] != 0) return bad("reserved grid fields must be zero");
+    if (grid->precision != PIC_FP64 && grid->precision != PIC_FP32_MIXED)
+        return bad("precision must be PIC_FP64 or PIC_FP32_MIXED");
+    if (grid->precision == PIC_FP32_MIXED &&
+        (grid->n[0] > 1024 || grid->n[1] > 1024 || grid->n[2] > 1024))
+        return bad("PIC_FP32_MIXED supports at most 1024 cells per dimension");
     const int S = grid->supercell;
     if (S < 1) return bad("supercell must be >= 1");
     if (grid->rebin_every < 1) return bad("rebin_every must be >= 1");
@@ -317,6 +343,7 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     g.h = h;
     g.dt = dt;
     c->R = grid->rebin_every;
+    c->precision = grid->precision;
 
     const size_t fb = (size_t)ncell * sizeof(double);
     for (int d = 0; d < 3; ++d) {
@@ -354,10 +381,28 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
             const double area = dx[(d + 1) % 3] * dx[(d + 2) % 3];
             st.c.jc[d] = qw / (dt * area);
         }
+        st.cm.h = (float)st.c.hq;
+        for (int d = 0; d < 3; ++d) {
+            st.cm.jc[d] = (float)st.c.jc[d];
+            st.cm.cdt[d] = (float)(dt / dx[d]);
+        }
         st.capacity = q.capacity;
         if (q.capacity > maxcap) maxcap = q.capacity;
         const size_t pb = (size_t)q.capacity * sizeof(double);
-        for (int b = 0; b < 2; ++b) {
+        const size_t fb4 = (size_t)q.capacity * sizeof(float);
+        for (int b = 0; b < 2 && c->precision == PIC_FP32_MIXED; ++b) {
+            PartsM& P = st.bufm[b];
+            if ((e = dalloc(c, (void**)&P.cell, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.ox, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.oy, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.oz, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.ux, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.uy, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.uz, fb4)) != hipSuccess ||
+                (e = dalloc(c, (void**)&P.id, (size_t)q.capacity * sizeof(int64_t))) != hipSuccess)
+                return cfail(hip_fail(c, e, "hipMalloc particles"));
+        }
+        for (int b = 0; b < 2 && c->precision == PIC_FP64; ++b) {
             Parts& P = st.buf[b];
             if ((e = dalloc(c, (void**)&P.x, pb)) != hipSuccess ||
                 (e = dalloc(c, (void**)&P.y, pb)) != hipSuccess ||
@@ -376,6 +421,11 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     if ((e = dalloc(c, (void**)&c->far_q, (size_t)(maxcap > 0 ? maxcap : 1) * sizeof(int))) !=
         hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc far queue"));
+    if (c->precision == PIC_FP32_MIXED)
+        for (int k = 0; k < 6; ++k)
+            if ((e = dalloc(c, (void**)&c->stage[k], (size_t)(maxcap > 0 ? maxcap : 1) *
+                                                         sizeof(double))) != hipSuccess)
+                return cfail(hip_fail(c, e, "hipMalloc staging"));
     c->scratch_bytes = rebin_scratch_bytes(maxcap, g);
     if ((e = dalloc(c, &c->scratch, c->scratch_bytes)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc sort scratch"));
@@ -416,32 +466,36 @@ int pic_load_particles(pic_ctx* c, int32_t species, int64_t n, const double* x, 
         bad_ptr(uz, n))
         return fail(c, PIC_EINVAL, "particle arrays must not be NULL");
     HIPCHK(c, hipSetDevice(c->device));
+    const bool mixed = c->precision == PIC_FP32_MIXED;
     Parts& P = s.buf[0];
+    int64_t* const idp = mixed ? s.bufm[0].id : P.id;
+    double* const dst[6] = {mixed ? c->stage[0] : P.x, mixed ? c->stage[1] : P.y,
+                            mixed ? c->stage[2] : P.z, mixed ? c->stage[3] : P.ux,
+                            mixed ? c->stage[4] : P.uy, mixed ? c->stage[5] : P.uz};
+    const double* const src[6] = {x, y, z, ux, uy, uz};
     const size_t b = (size_t)n * sizeof(double);
+    HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(unsigned), c->stream));
     if (n > 0) {
-        HIPCHK(c, hipMemcpyAsync(P.x, x, b, hipMemcpyDefault, c->stream));
-        HIPCHK(c, hipMemcpyAsync(P.y, y, b, hipMemcpyDefault, c->stream));
-        HIPCHK(c, hipMemcpyAsync(P.z, z, b, hipMemcpyDefault, c->stream));
-        HIPCHK(c, hipMemcpyAsync(P.ux, ux, b, hipMemcpyDefault, c->stream));
-        HIPCHK(c, hipMemcpyAsync(P.uy, uy, b, hipMemcpyDefault, c->stream));
-        HIPCHK(c, hipMemcpyAsync(P.uz, uz, b, hipMemcpyDefault, c->stream));
+        for (int k = 0; k < 6; ++k)
+            HIPCHK(c, hipMemcpyAsync(dst[k], src[k], b, hipMemcpyDefault, c->stream));
         if (id) {
-            HIPCHK(c, hipMemcpyAsync(P.id, id, (size_t)n * sizeof(int64_t), hipMemcpyDefault,
+            HIPCHK(c, hipMemcpyAsync(idp, id, (size_t)n * sizeof(int64_t), hipMemcpyDefault,
                                      c->stream));
         } else {
             int nb = (int)((n + 255) / 256);
             if (nb > 65536) nb = 65536;
-            hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(256), 0, c->stream, P.id, n);
+            hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(256), 0, c->stream, idp, n);
             HIPCHK(c, hipGetLastError());
         }
+        if (mixed)
+            HIPCHK(c, launch_to_mixed(c->g, n, c->stage, s.bufm[0], s.keys, c->d_err, c->stream));
     }
-    HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(unsigned), c->stream));
     s.n = n;
     s.cur = 0;
     s.pending = false;
     {
         Timed t(c, ST_SORT);
-        int r = do_sort(c, s, nullptr);
+        int r = do_sort(c, s, mixed ? s.keys : nullptr);
         if (r == PIC_OK) r = resolve_pending(c, s);
         if (r != PIC_OK) return r;
     }
@@ -500,28 +554,43 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
             const bool sort_after = (c->steps_since_sort + 1 == c->R);
             for (auto& s : c->sp) {
                 if (s.n == 0) continue;
+                const bool mixed = c->precision == PIC_FP32_MIXED;
                 const Parts& src = s.buf[s.cur];
                 const Parts& dst = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
+                const PartsM& srcm = s.bufm[s.cur];
+                const PartsM& dstm = s.pending ? s.bufm[1 - s.cur] : s.bufm[s.cur];
                 const unsigned* perm = s.pending ? s.perm : nullptr;
                 unsigned* keys = sort_after ? s.keys : nullptr;
                 unsigned* fn = c->far_n + c->far_phase;
                 unsigned* fn_next = c->far_n + (1 - c->far_phase);
                 {
                     Timed t(c, s.pending ? ST_PUSH_PERM : ST_PUSH);
-                    HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, perm, keys, s.sc_off, f, Jd,
-                                                  c->d_err, c->d_nfar, c->far_q, fn, fn_next,
-                                                  c->stream));
+                    if (mixed)
+                        HIPCHK(c, launch_push_mixed(c->g, s.cm, srcm, dstm, perm, keys, s.sc_off,
+                                                    f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
+                                                    fn_next, c->stream));
+                    else
+                        HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, perm, keys, s.sc_off,
+                                                      f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
+                                                      fn_next, c->stream));
                 }
                 {
                     Timed t(c, ST_FAR);
-                    HIPCHK(c, launch_far_movers(c->g, s.c, src, dst, perm, keys, f, Jd, c->d_err,
-                                                c->d_nfar, c->far_q, fn, fn_next, c->stream));
+                    if (mixed)
+                        HIPCHK(c, launch_far_mixed(c->g, s.cm, srcm, dstm, perm, keys, f, Jd,
+                                                   c->d_err, c->d_nfar, c->far_q, fn, fn_next,
+                                                   c->stream));
+                    else
+                        HIPCHK(c, launch_far_movers(c->g, s.c, src, dst, perm, keys, f, Jd,
+                                                    c->d_err, c->d_nfar, c->far_q, fn, fn_next,
+                                                    c->stream));
                 }
                 c->far_phase = 1 - c->far_phase;
                 if (c->timers) (s.pending ? c->push_perm_launches : c->push_launches)++;
                 if (s.pending) {
                     Timed t(c, ST_SORT);
-                    HIPCHK(c, launch_permute_ids(s.n, s.perm, src.id, dst.id, c->stream));
+                    HIPCHK(c, launch_permute_ids(s.n, s.perm, mixed ? srcm.id : src.id,
+                                                 mixed ? dstm.id : dst.id, c->stream));
                     s.cur = 1 - s.cur;
                     s.pending = false;
                 }
@@ -583,7 +652,8 @@ int pic_get_particles(pic_ctx* c, int32_t species, int64_t capacity, int64_t* n_
         int r = resolve_pending(c, s);
         if (r != PIC_OK) return r;
     }
-    const Parts& P = s.buf[s.cur];
+    Parts P;
+    HIPCHK(c, fp64_view(c, s, P));
     const size_t b = (size_t)s.n * sizeof(double);
     double* dst[6] = {x, y, z, ux, uy, uz};
     const double* src[6] = {P.x, P.y, P.z, P.ux, P.uy, P.uz};
@@ -620,14 +690,16 @@ int pic_diagnostics(pic_ctx* c, double out[8]) {
         const SpeciesState& s = c->sp[k];
         qtot += s.c.q * s.c.w * (double)s.n;
         if (s.n == 0) continue;
-        const Parts& P = s.buf[s.cur];
+        Parts P;
+        HIPCHK(c, fp64_view(c, s, P));
         HIPCHK(c, launch_kinetic(P.ux, P.uy, P.uz, s.n, c->d_acc + 2 + k, c->stream));
     }
     // rho, Gauss residual and div B against the references
     HIPCHK(c, launch_zero(c->rho, nc, c->stream));
     for (auto& s : c->sp) {
         if (s.n == 0) continue;
-        const Parts& P = s.buf[s.cur];
+        Parts P;
+        HIPCHK(c, fp64_view(c, s, P));
         HIPCHK(c, launch_rho(c->g, (s.c.q * s.c.w) / dv, P.x, P.y, P.z, s.n, c->rho, c->stream));
     }
     Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
@@ -699,7 +771,7 @@ int pic_get_counters(pic_ctx* c, int64_t out[4]) {
     out[0] = (int64_t)nfar;
     out[1] = c->rebins;
     out[2] = c->steps;
-    out[3] = push_deposit_lds_bytes(c->g);
+    out[3] = c->precision == PIC_FP64 ? push_deposit_lds_bytes(c->g) : push_mixed_lds_bytes(c->g);
     return PIC_OK;
 }
 

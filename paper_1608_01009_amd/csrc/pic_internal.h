@@ -50,6 +50,25 @@ struct Fields {
     double* B[3];
 };
 
+// Mixed-precision variant: per-species FP32 constants and the packed particle
+// arrays (cell = i | j << 10 | k << 20, offsets in [0, 1), momenta).
+struct SpeciesM {
+    float h;           // (float)(q dt / (2 m))
+    float jc[3];       // (float)(q w / (dt * face area of the d face))
+    float cdt[3];      // (float)(dt / dx_d)
+};
+
+struct PartsM {
+    unsigned* cell;
+    float* ox;
+    float* oy;
+    float* oz;
+    float* ux;
+    float* uy;
+    float* uz;
+    int64_t* id;
+};
+
 // ---- launchers (implemented in the kernel translation units) --------------
 
 // Gather + Boris + advance + VB deposit + wrap for every particle of one
@@ -75,6 +94,30 @@ hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src
                              unsigned* far_n_next, hipStream_t s);
 int push_deposit_lds_bytes(const Geom& g);
 bool push_deposit_supported(int S, int h);
+
+// Mixed-precision counterparts of launch_push_deposit / launch_far_movers
+// (same contracts, packed particle arrays, FP32 tiles and arithmetic).
+hipError_t launch_push_mixed(const Geom& g, const SpeciesM& sp, const PartsM& src,
+                             const PartsM& dst, const unsigned* perm, unsigned* keys,
+                             const int* sc_off, const Fields& f, double* const J[3],
+                             unsigned* err, unsigned long long* nfar, int* far_q,
+                             unsigned* far_n, unsigned* far_n_next, hipStream_t s);
+hipError_t launch_far_mixed(const Geom& g, const SpeciesM& sp, const PartsM& src,
+                            const PartsM& dst, const unsigned* perm, unsigned* keys,
+                            const Fields& f, double* const J[3], unsigned* err,
+                            unsigned long long* nfar, int* far_q, unsigned* far_n,
+                            unsigned* far_n_next, hipStream_t s);
+int push_mixed_lds_bytes(const Geom& g);
+// FP64 positions / momenta (device arrays x, y, z, ux, uy, uz) -> packed
+// arrays and sort keys; ERR_BADPOS for positions outside [0, n), non-finite
+// values or momenta beyond FP32 range.
+hipError_t launch_to_mixed(const Geom& g, int64_t n, const double* const x[6], const PartsM& dst,
+                           unsigned* keys, unsigned* err, hipStream_t s);
+// packed arrays -> FP64 positions (cell + offset, exact) and momenta
+hipError_t launch_to_double(int64_t n, const PartsM& src, double* const x[6], hipStream_t s);
+// dst[i] = src[perm[i]] for the packed arrays and the ids
+hipError_t launch_permute_mixed(int64_t n, const unsigned* perm, const PartsM& src,
+                                const PartsM& dst, hipStream_t s);
 
 // Yee update from the fields f into fo (distinct arrays); also clears Jclear
 // (the buffer the next step deposits into).

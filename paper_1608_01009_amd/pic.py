@@ -21,6 +21,10 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpic_hip.so")
 
 PIC_OK = 0
 PIC_EINVAL = -1
+PIC_FP64 = 0
+PIC_FP32_MIXED = 1
+_PRECISION = {"fp64": PIC_FP64, "mixed": PIC_FP32_MIXED, PIC_FP64: PIC_FP64,
+              PIC_FP32_MIXED: PIC_FP32_MIXED}
 PIC_ENOMEM = -2
 PIC_EDEVICE = -3
 PIC_ECAPACITY = -4
@@ -37,7 +41,8 @@ ABI_SYMBOLS = ("pic_create", "pic_load_particles", "pic_set_fields", "pic_step",
 
 class PicGrid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("supercell", C.c_int32), ("rebin_every", C.c_int32),
-                ("halo", C.c_int32), ("reserved", C.c_int32 * 4), ("stream", C.c_void_p)]
+                ("halo", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32 * 3),
+                ("stream", C.c_void_p)]
 
 
 class PicSpecies(C.Structure):
@@ -126,10 +131,11 @@ def _torch_stream():
 
 
 def pic_create(n: Sequence[int], dx: Sequence[float], dt: float, species, *, supercell: int = 4,
-               rebin_every: int = 20, halo: int = 0, stream=None):
+               rebin_every: int = 20, halo: int = 0, stream=None, precision="fp64"):
     """``species``: sequence of ``(charge, mass, weight, capacity)``.
     ``stream``: None (library-owned stream), ``"torch"`` (torch's current
-    stream) or a raw ``hipStream_t`` integer.  Returns the context handle."""
+    stream) or a raw ``hipStream_t`` integer.  ``precision``: "fp64" or
+    "mixed" (PIC_FP32_MIXED).  Returns the context handle."""
     L = library()
     g = PicGrid()
     for d in range(3):
@@ -137,6 +143,7 @@ def pic_create(n: Sequence[int], dx: Sequence[float], dt: float, species, *, sup
     g.supercell = int(supercell)
     g.rebin_every = int(rebin_every)
     g.halo = int(halo)
+    g.precision = _PRECISION[precision] if precision in _PRECISION else int(precision)
     if stream == "torch":
         stream = _torch_stream()
     g.stream = stream
@@ -239,12 +246,14 @@ def pic_destroy(ctx):
 class Simulation:
     """Owning convenience wrapper around one context."""
 
-    def __init__(self, n, dx, dt, species, *, supercell=4, rebin_every=20, halo=0, stream=None):
+    def __init__(self, n, dx, dt, species, *, supercell=4, rebin_every=20, halo=0, stream=None,
+                 precision="fp64"):
         self.n = tuple(int(v) for v in n)
         self.ncell = self.n[0] * self.n[1] * self.n[2]
         self.species = [tuple(s) for s in species]
+        self.precision = precision
         self.ctx = pic_create(n, dx, dt, species, supercell=supercell, rebin_every=rebin_every,
-                              halo=halo, stream=stream)
+                              halo=halo, stream=stream, precision=precision)
 
     @classmethod
     def from_workload(cls, wl, capacity_factor=1.0, **kw):

@@ -56,6 +56,8 @@ def _create(**kw):
     (dict(species=[(-1.0, 1.0, -0.1, 10)]), "weight"),
     (dict(species=[(-1.0, 1.0, 0.1, -1)]), "capacity"),
     (dict(species=[(1e-280, 1.0, 0.1, 10)]), "charge dt"),
+    (dict(precision=2), "precision"),
+    (dict(precision="mixed", n=(2048, 8, 8)), "1024 cells"),
     (dict(species=[(-1.0, 1e-280, 0.1, 10)]), "charge dt"),
     (dict(species=[]), "n_species"),
 ])

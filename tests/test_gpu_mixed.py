@@ -1,0 +1,230 @@
+"""GPU mixed-precision variant (PIC_FP32_MIXED) against the oracle's
+mixed-precision loop and against the FP64 oracle, through the C ABI.
+
+One step from an identical state (the GPU's state S_k read back; the oracle
+steps from it; compared with the GPU's S_{k+1}):
+* ids (the stored order) and positions (cell + FP32 offset) and FP32 momenta:
+  bit for bit against the mixed-precision oracle (same FP32 expressions);
+* J per node: |J_gpu - J_oracle| <= (n_node + 4) 2^-24 sum_node |contribution|,
+  the bound of summing n_node FP32 contributions in another order plus a few
+  units of rounding in each contribution (the GPU multiplies by 1/12 where
+  the oracle divides by 12);
+* E and B: the J bound carried through one Yee update.
+Against the FP64 oracle the same step differs by FP32 rounding: positions,
+momenta and J within the bounds the oracle pins use; the observed errors are
+printed.
+"""
+import numpy as np
+import pytest
+
+from paper_1608_01009_amd import pic
+from paper_1608_01009_amd import workloads as W
+
+from gpu_parity_util import KEYS, log, read_state
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+def _mixed_oracle(wl, precision="mixed"):
+    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+                         S=wl.S, R=wl.R, precision=precision)
+    o.collect_abs = precision == "mixed"
+    return o
+
+
+def _compare_mixed(gF, gP, o, wl, tag):
+    for s, gp in enumerate(gP):
+        op = o.particles(s)
+        n = gp["n"]
+        assert n == len(op["x"]), tag
+        assert np.array_equal(gp["id"][:n], op["id"]), f"{tag}: order differs"
+        for k in ("x", "y", "z", "ux", "uy", "uz"):
+            assert np.array_equal(gp[k][:n], op[k]), (
+                f"{tag}: {k} differs, max {np.max(np.abs(gp[k][:n] - op[k]))}")
+    tolJ = []
+    for d in range(3):
+        g = gF[6 + d]
+        w = o.F[6 + d]
+        bound = (o.Jcnt[d] + 4) * EPS32 * o.Jabs[d]
+        err = np.abs(g - w)
+        assert np.all(err <= bound + 1e-300), (
+            f"{tag}: J{'xyz'[d]} max excess {np.max(err - bound)}")
+        tolJ.append(np.max(bound))
+    dt = wl.dt
+    tE = dt * max(tolJ) * 1.01
+    for c in range(3):
+        scale = np.max(np.abs(o.F[c]))
+        assert np.max(np.abs(gF[c] - o.F[c])) <= tE + 1e-12 * scale, f"{tag}: E{'xyz'[c]}"
+    tB = 2.0 * dt * tE / min(wl.dx)
+    for c in range(3, 6):
+        scale = np.max(np.abs(o.F[c]))
+        assert np.max(np.abs(gF[c] - o.F[c])) <= tB + 1e-12 * scale, f"{tag}: B{'xyz'[c - 3]}"
+
+
+def _run(wl, ks, check, sim_kwargs=None):
+    sim = pic.Simulation.from_workload(wl, precision="mixed", **(sim_kwargs or {}))
+    nsp = len(wl.species)
+    cur = 0
+    try:
+        for k in ks:
+            log(f"  mixed {wl.name}: advancing GPU to step {k}")
+            if k > cur:
+                sim.step(k - cur)
+            F, P = read_state(sim, nsp)
+            sim.step(1)
+            cur = k + 1
+            gF, gP = read_state(sim, nsp)
+            check(wl, k, F, P, gF, gP)
+        return int(sim.counters()[0])
+    finally:
+        sim.close()
+
+
+def _against_mixed_oracle(wl, k, F, P, gF, gP):
+    o = _mixed_oracle(wl)
+    o.set_state([[p[key][:p["n"]] for key in KEYS] for p in P], F[:6], k % wl.R)
+    o.step(1)
+    _compare_mixed(gF, gP, o, wl, f"{wl.name} k={k}")
+    log(f"  mixed {wl.name} k={k}: positions, momenta, ids bit for bit; J, E, B within bounds")
+
+
+def test_mixed_one_step_bit_exact_against_mixed_oracle():
+    _run(W.scaled(2, (16, 16, 16), 20, seed=41), [0, 1, 19, 20], _against_mixed_oracle)
+
+
+def test_mixed_two_species_ragged():
+    base = W.scaled(2, (8, 8, 16), 9, seed=42)
+    ions = W.scaled(2, (8, 8, 16), 3, seed=43)
+    sp_i = ions.species[0]
+    sp_i.charge, sp_i.mass = 1.0, 1836.0
+    for k in ("ux", "uy", "uz"):
+        setattr(sp_i, k, getattr(sp_i, k) * 0.02)
+    for k in ("x", "y", "z", "ux", "uy", "uz"):
+        setattr(base.species[0], k, np.ascontiguousarray(getattr(base.species[0], k)[:9 * 1024 - 7]))
+    base.species.append(sp_i)
+    _run(base, [0, 19], _against_mixed_oracle)
+
+
+@pytest.mark.parametrize("n,S,h", [((4, 4, 4), 4, 1), ((8, 8, 8), 2, 2), ((6, 6, 6), 1, 1),
+                                   ((16, 8, 8), 4, 2)])
+def test_mixed_supercell_and_halo_shapes(n, S, h):
+    wl = W.plasma(f"mixed-shape-{n}-S{S}-h{h}", n, 9, 0.05, seed=50 + S, noise=1e-3, S=S, R=7)
+    _run(wl, [0, 6], _against_mixed_oracle, sim_kwargs=dict(halo=h))
+
+
+def test_mixed_anisotropic_cells():
+    dx = (1.0, 0.5, 2.0)
+    wl = W.plasma("mixed-aniso", (8, 16, 4), 6, 0.05, seed=52, noise=1e-3, dx=dx,
+                  dt=W.courant_dt(dx, 0.9))
+    _run(wl, [0, 3], _against_mixed_oracle)
+
+
+def test_mixed_far_movers():
+    # a relativistic beam drifts more than the halo before the next re-sort
+    wl = W.plasma("mixed-beam", (16, 16, 16), 2, 0.0, seed=53, noise=1e-2, R=40)
+    sp = wl.species[0]
+    rng = np.random.default_rng(54)
+    sp.ux[:] = 4.0 + rng.random(sp.n)
+    sp.uy[:] = -3.0
+    sp.uz[:] = 2.0 * rng.standard_normal(sp.n)
+    nfar = _run(wl, [0, 8, 30], _against_mixed_oracle)
+    assert nfar > 0
+
+
+def test_mixed_clustered_and_empty():
+    n = (8, 8, 8)
+    rng = np.random.default_rng(62)
+    N = 1500
+    x = rng.random(N) * 4.0
+    y = rng.random(N) * 4.0
+    z = 4.0 + rng.random(N) * 4.0
+    x[::2] += 4.0
+    u = rng.normal(0, 0.1, (N, 3))
+    fields = [rng.uniform(-1e-2, 1e-2, 512) for _ in range(6)]
+    wl = W.Workload("mixed-clustered", n, (1.0, 1.0, 1.0), W.courant_dt(), 4, 20, 10,
+                    [W.Species(-1.0, 1.0, 0.05, x, y, z, u[:, 0].copy(), u[:, 1].copy(),
+                               u[:, 2].copy()),
+                     W.Species(1.0, 1836.0, 0.05, np.zeros(0), np.zeros(0), np.zeros(0),
+                               np.zeros(0), np.zeros(0), np.zeros(0))],
+                    fields)
+    _run(wl, [0, 2], _against_mixed_oracle)
+
+
+def test_mixed_against_fp64_oracle_error_statement():
+    wl = W.scaled(2, (16, 16, 16), 20, seed=44)
+    errs = {}
+
+    def check(wl, k, F, P, gF, gP):
+        o = _mixed_oracle(wl, precision="fp64")
+        o.set_state([[p[key][:p["n"]] for key in KEYS] for p in P], F[:6], k % wl.R)
+        o.step(1)
+        om = _mixed_oracle(wl)               # for the per-node J bounds
+        om.set_state([[p[key][:p["n"]] for key in KEYS] for p in P], F[:6], k % wl.R)
+        om.step(1)
+        gp, op = gP[0], o.particles(0)
+        n = gp["n"]
+        assert np.array_equal(gp["id"][:n], op["id"])
+        umax = max(np.max(np.abs(op[k])) for k in ("ux", "uy", "uz"))
+        sp = wl.species[0]
+        h = abs(sp.charge * wl.dt / (2 * sp.mass))
+        emax = max(np.max(np.abs(f)) for f in F[:3])
+        for d, key in enumerate(("x", "y", "z")):
+            dx = np.abs(gp[key][:n] - op[key])
+            dx = np.minimum(dx, wl.n[d] - dx)
+            errs[key] = float(dx.max())
+            assert dx.max() <= 4 * EPS32 * (1.0 + wl.dt * umax), key
+        for key in ("ux", "uy", "uz"):
+            du = np.abs(gp[key][:n] - op[key])
+            errs[key] = float(du.max())
+            assert du.max() <= 8 * EPS32 * (umax + h * emax), key
+        for d in range(3):
+            err = np.abs(gF[6 + d] - o.F[6 + d])
+            errs[f"J{'xyz'[d]}/max|J|"] = float(err.max() / np.max(np.abs(o.F[6 + d])))
+            assert np.all(err <= (om.Jcnt[d] + 68) * EPS32 * om.Jabs[d] + 1e-300)
+        for c, name in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+            errs[name + "/max"] = float(np.max(np.abs(gF[c] - o.F[c])) / np.max(np.abs(o.F[c])))
+        log(f"  mixed vs FP64 oracle, one step from S_{k}: {errs}")
+
+    _run(wl, [0, 20], check)
+
+
+def test_mixed_long_run_against_fp64_gpu():
+    # 200 steps of the 64^3 x 50 ppc recipe at 16^3 x 20 ppc in both
+    # precisions from the same (mixed-rounded) state: energies, total
+    # momentum and the Gauss drift; the trajectories decorrelate (the plasma
+    # is chaotic), so only ensemble quantities are compared
+    wl = W.scaled(2, (16, 16, 16), 20, seed=45)
+    sp = wl.species[0]
+    o = _mixed_oracle(wl)
+    xr = o.to_mixed([sp.x, sp.y, sp.z, sp.ux, sp.uy, sp.uz])
+    sp.x, sp.y, sp.z, sp.ux, sp.uy, sp.uz = [np.ascontiguousarray(a) for a in xr]
+    out = {}
+    for prec in ("fp64", "mixed"):
+        sim = pic.Simulation.from_workload(wl, precision=prec)
+        try:
+            d0 = sim.diagnostics()
+            sim.step(200)
+            d = sim.diagnostics()
+            P = sim.particles(0)
+            n = P["n"]
+            mom = [float(np.sum(P[k][:n])) for k in ("ux", "uy", "uz")]
+            # the mean charge density is n0 = 1, so the Gauss drift is
+            # relative to the density scale
+            out[prec] = dict(WE=d[0], WB=d[1], K=d[2], Q=d[3], gauss=d[4], divB=d[5], mom=mom,
+                             K0=d0[2])
+        finally:
+            sim.close()
+    a, b = out["fp64"], out["mixed"]
+    log(f"  200 steps, FP64: {a}")
+    log(f"  200 steps, mixed: {b}")
+    assert a["Q"] == b["Q"]
+    assert a["gauss"] <= 1e-12
+    # FP32 rounding of J breaks exact continuity: a random walk of ~1e-7
+    # relative per step
+    assert b["gauss"] <= 1e-4
+    for key in ("WE", "K"):
+        assert abs(a[key] - b[key]) <= 1e-2 * abs(a[key]), key
