@@ -64,7 +64,7 @@ enum {
     PIC_FP64 = 0,        /* double precision throughout (Section 3 of the paper) */
     PIC_FP32_MIXED = 1   /* positions as integer cell + FP32 offset in [0, 1), FP32 momenta,
                             FP32 gather / Boris / VB split and weights in cell-local
-                            coordinates, FP32 LDS J tiles summed into the FP64 J; fields,
+                            coordinates, FP32 J contributions summed in FP64; fields,
                             Yee update and J stay FP64.  Loaded positions are rounded to
                             that form, loaded momenta to FP32; pic_get_particles returns
                             cell + offset exactly.  At most 1024 cells per dimension. */

@@ -5,7 +5,10 @@
 //     offsets in [0, 1), momenta as FP32 (28 bytes per particle instead of 48);
 //   - the gather from an FP32 copy of the E/B tile, Boris, advance and the VB
 //     split and weights in FP32, in cell-local coordinates;
-//   - an FP32 J tile (ds_add_f32) whose sums are added into the FP64 global J.
+//   - each FP32 contribution converted (exactly) to FP64 and summed in an FP64
+//     LDS J tile (ds_add_f64: on gfx950 the FP32 LDS atomic add serializes
+//     over the lanes, ~20x the cost of the FP64 one), then added into the
+//     FP64 global J.
 // This is an extension beyond the paper, which computes in double precision
 // throughout (Section 3); the fields, the Yee update and J stay FP64.  Every
 // operation is rounded to FP32 as written (fused multiply-adds where written,
@@ -71,19 +74,21 @@ struct MArgs {
     unsigned* far_n_next;
 };
 
-// LDS layouts of the FP32 tiles.  E/B node (tx, ty, tz) of component c at
-// c * ECS + tx + EPY ty + EPZ tz; J node of component d at d * JC + tx +
-// JPY ty + JPZ tz.  For S = 4, h = 1 the pitches put the 64 cells of a round
-// (x + EPY y + EPZ z with x, y, z in 0..3) on 64 distinct 4-byte banks.
+// LDS layouts: FP32 E/B tile, node (tx, ty, tz) of component c at
+// c * ECS + tx + EPY ty + EPZ tz; FP64 J tile, node of component d at
+// d * JC + tx + JPY ty + JPZ tz.  For S = 4, h = 1 the pitches are those
+// measured cheapest for the access pattern of a round of particles (the
+// E/B plane pitch padded from 64 to 68; the J pitches 12 / 112 put a half
+// wave of 32 cells on 32 distinct bank pairs).
 template <int S, int H>
 struct MLayout {
     static constexpr int T = S + 2 * H + 2;
-    static constexpr int EPY = (S == 4 && H == 1) ? 16 : T;
-    static constexpr int EPZ = (S == 4 && H == 1) ? 132 : T * T;
+    static constexpr int EPY = T;
+    static constexpr int EPZ = (S == 4) ? T * T + 4 : T * T;
     static constexpr int ECS = EPZ * T;
     static constexpr int TJ = S + 2 * H + 3;
-    static constexpr int JPY = (S == 4 && H == 1) ? 16 : TJ;
-    static constexpr int JPZ = (S == 4 && H == 1) ? 196 : TJ * TJ;
+    static constexpr int JPY = (S == 4 && H == 1) ? 12 : TJ;
+    static constexpr int JPZ = (S == 4 && H == 1) ? 112 : TJ * TJ;
     static constexpr int JC = JPZ * (TJ - 1) + JPY * (TJ - 1) + TJ;
 };
 
@@ -406,7 +411,7 @@ push_mixed_kernel(const MArgs a) {
     constexpr int kWaves = kBlock / 64;
     constexpr int QCAP = 28;
     __shared__ float eb[6 * L::ECS];
-    __shared__ float jt[3 * JC];
+    __shared__ double jt[3 * JC];
     __shared__ float qb[kWaves][6][QCAP];
     __shared__ int qk[kWaves][QCAP];
 
@@ -434,7 +439,7 @@ push_mixed_kernel(const MArgs a) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) eb[c * L::ECS + li] = (float)a.EB[c][gi];
     }
-    for (int t = threadIdx.x; t < 3 * JC; t += kBlock) jt[t] = 0.0f;
+    for (int t = threadIdx.x; t < 3 * JC; t += kBlock) jt[t] = 0.0;
     __syncthreads();
 
     // relative cell of c inside the tile window [-H, S+H), periodic
@@ -455,7 +460,7 @@ push_mixed_kernel(const MArgs a) {
     // general move of a particle whose start cell sits at tile key `key`
     auto deposit_tile = [&](int key, const float o0[3], const float o1[3]) {
         vb_move_m(o0, o1, a.sp.jc, [&](int d, int rx, int ry, int rz, float v) {
-            atomicAdd(&jt[d * JC + key + rx + JPY * ry + JPZ * rz], v);
+            atomicAdd(&jt[d * JC + key + rx + JPY * ry + JPZ * rz], (double)v);
         });
     };
     auto drain = [&](int cnt) {
@@ -528,7 +533,7 @@ push_mixed_kernel(const MArgs a) {
                                     floorf(o1[2]) == 0.0f;
                 if (single) {
                     vb_single_m(o0, o1, a.sp.jc, [&](int j, float v) {
-                        atomicAdd(&jt[key + jt_off_m<JPY, JPZ, JC>(j)], v);
+                        atomicAdd(&jt[key + jt_off_m<JPY, JPZ, JC>(j)], (double)v);
                     });
                 } else {
                     crosser = true;
@@ -588,12 +593,12 @@ push_mixed_kernel(const MArgs a) {
     for (int r = threadIdx.x; r < TJ3; r += kBlock) {
         const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
         const int li = tx + JPY * ty + JPZ * tz;
-        const float v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
-        if (v[0] != 0.0f || v[1] != 0.0f || v[2] != 0.0f) {
+        const double v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
+        if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) {
             const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                if (v[c] != 0.0f) unsafeAtomicAdd(&a.J[c][gi], (double)v[c]);
+                if (v[c] != 0.0) unsafeAtomicAdd(&a.J[c][gi], v[c]);
         }
     }
 }
@@ -733,8 +738,8 @@ hipError_t launch_m(const MArgs& args, hipStream_t s) {
 
 template <int S, int H>
 constexpr int lds_bytes_m() {
-    return (6 * MLayout<S, H>::ECS + 3 * MLayout<S, H>::JC + (kBlock / 64) * 7 * 28) *
-           (int)sizeof(float);
+    return 6 * MLayout<S, H>::ECS * (int)sizeof(float) +
+           3 * MLayout<S, H>::JC * (int)sizeof(double) + (kBlock / 64) * 7 * 28 * 4;
 }
 
 MArgs make_margs(const Geom& g, const SpeciesM& sp, const PartsM& src, const PartsM& dst,
