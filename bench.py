@@ -11,7 +11,10 @@ timed region starts.
 Prints one JSON line with the throughput (particle updates/s), the roofline
 of the dominant kernel (push+deposit, HBM-bound: algorithmic bytes per launch
 over its average duration measured with HIP events on the library's stream),
-and the oracle's throughput on the host as a reported CPU baseline.
+the oracle's throughput on the host as a reported CPU baseline, and under
+"fp32_mixed" the same measurement of the mixed-precision variant
+(PIC_FP32_MIXED: integer cell + FP32 offsets and momenta, FP64 fields and J)
+on the same workload.
 """
 from __future__ import annotations
 
@@ -37,11 +40,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_launch(nparticles: int, ncell: int) -> int:
-    """Per particle: read and write x, y, z, ux, uy, uz (2 x 48 B).  Per cell:
-    read the six E/B components and add the three J components once
-    (9 x 8 B)."""
-    return nparticles * 96 + ncell * 72
+def algorithmic_bytes_per_launch(nparticles: int, ncell: int, precision: str = "fp64") -> int:
+    """Per particle: read and write the state once: x, y, z, ux, uy, uz in
+    FP64 (2 x 48 B), or the packed cell + three FP32 offsets + three FP32
+    momenta of the mixed-precision variant (2 x 28 B).  Per cell: read the six
+    FP64 E/B components and add the three FP64 J components once (9 x 8 B)."""
+    per_particle = 96 if precision == "fp64" else 56
+    return nparticles * per_particle + ncell * 72
 
 
 def measured_traffic():
@@ -82,6 +87,39 @@ def cpu_baseline(wl, steps: int):
                       f"cells), single-threaded C oracle, {dt:.2f} s"}
 
 
+def mixed_leg(wl, args):
+    """The same workload and timing with the mixed-precision particle loop
+    (PIC_FP32_MIXED): a separate context, the same step count."""
+    from paper_1608_01009_amd import pic
+    import torch
+    n = wl.nparticles
+    log(f"fp32-mixed: loading, warmup {args.warmup} steps")
+    sim = pic.Simulation.from_workload(wl, precision="mixed")
+    sim.step(args.warmup)
+    pic.pic_enable_timers(sim.ctx, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = pic.pic_get_timers(sim.ctx)
+    d = sim.diagnostics()
+    sim.close()
+    push_ms_avg = tm[0] / max(tm[1], 1)
+    bytes_launch = algorithmic_bytes_per_launch(n, wl.ncells, "mixed")
+    achieved = bytes_launch / (push_ms_avg * 1e-3) / 1e9
+    log(f"fp32-mixed: wall {wall*1e3:.2f} ms for {args.steps} steps; push+deposit "
+        f"{push_ms_avg*1e3:.1f} us/launch; gauss drift {d[4]:.3e}")
+    return {"value": n * args.steps / wall, "unit": "particle updates/s",
+            "ms_per_step": wall * 1e3 / args.steps, "dtype": "f32 (FP64 fields and J)",
+            "roofline": {"bound": "hbm", "kernel": "push_mixed_kernel<4, 1, false>",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_launch": bytes_launch,
+                         "avg_launch_us": push_ms_avg * 1e3},
+            "gauss_drift": d[4]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32-mixed leg (same workload, PIC_FP32_MIXED)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -170,6 +210,8 @@ def main():
                      "avg_launch_us": push_ms_avg * 1e3},
         "cpu_baseline": None,
     }
+    if not args.no_mixed:
+        rec["fp32_mixed"] = mixed_leg(wl, args)
     if args.copy_calibration_mib > 0:
         nel = args.copy_calibration_mib * (1 << 20) // 8
         a = torch.ones(nel, dtype=torch.float64, device="cuda")
