@@ -70,6 +70,18 @@ enum {
                             cell + offset exactly.  At most 1024 cells per dimension. */
 };
 
+/* Current accumulation.  With deterministic_j = 0 every J contribution is
+ * added with FP64 atomics (LDS tile, then global), so J (and through it E, B
+ * and the particles) can differ in the last bits from run to run.  With
+ * deterministic_j = 1 each FP64 contribution v is split exactly into two
+ * integers, hi = rint(v 2^k) and lo = rint((v 2^k - hi) 2^16), summed with
+ * integer atomics, and J = hi 2^-k + lo 2^-(k+16): the sums do not depend on
+ * the order, so the whole run is bit-reproducible (the scale 2^k is chosen at
+ * creation from the capacities and charges so that no sum overflows; each J
+ * value carries an error below 2^-(k+17) per contribution, i.e. about 2^-17
+ * of the FP64 rounding of the largest possible contribution).  Limit: at most
+ * 16383 particles of a species per supercell (PIC_ECAPACITY from pic_step). */
+
 typedef struct {
     int32_t n[3];           /* cells per dimension; each a multiple of `supercell` */
     int32_t supercell;      /* S: supercell edge in cells (Section 4.3); 1..6 with halo 1,
@@ -77,7 +89,9 @@ typedef struct {
     int32_t rebin_every;    /* R >= 1: stable re-sort after every R-th step since the last sort */
     int32_t halo;           /* h: drift margin in cells of the per-supercell LDS tiles; 0 -> 1 */
     int32_t precision;      /* PIC_FP64 or PIC_FP32_MIXED */
-    int32_t reserved[3];    /* must be zero */
+    int32_t deterministic_j;  /* 1: bit-reproducible current accumulation (below); 0: FP64
+                                 atomics (sums in arbitrary order) */
+    int32_t reserved[2];    /* must be zero */
     void* stream;           /* hipStream_t to run on, or NULL for a library-owned stream */
 } pic_grid_t;
 

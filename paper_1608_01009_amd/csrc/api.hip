@@ -57,6 +57,7 @@ __global__ void iota_kernel(int64_t* id, int64_t n) {
 struct pic_ctx {
     int device = 0;
     int precision = PIC_FP64;
+    DetJ det{};              // deterministic J: integer accumulators (hi[0] == nullptr: off)
     double* stage[6] = {};   // mixed precision: FP64 staging of x, y, z, ux, uy, uz
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -198,6 +199,9 @@ int sync_and_check(pic_ctx* c, bool stepping) {
     const unsigned e = *c->h_err;
     if (e & ERR_NONFINITE)
         return fail(c, PIC_ENONFINITE, "a particle state became non-finite during a step");
+    if (e & ERR_DETCAP)
+        return fail(c, PIC_ECAPACITY,
+                    "deterministic J: a supercell holds more than 16383 particles of one species");
     if (e & ERR_BADPOS)
         return fail(c, stepping ? PIC_ENONFINITE : PIC_EINVAL,
                     "particle positions must be finite and inside [0, n) with finite momenta");
@@ -271,8 +275,10 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     if (!grid || !dx) return bad("grid and dx must not be NULL");
     if (n_species < 1 || n_species > 64 || !species)
         return bad("n_species must be in [1, 64] with a species array");
-    for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 2; ++r)
         if (grid->reserved[r] != 0) return bad("reserved grid fields must be zero");
+    if (grid->deterministic_j != 0 && grid->deterministic_j != 1)
+        return bad("deterministic_j must be 0 or 1");
     if (grid->precision != PIC_FP64 && grid->precision != PIC_FP32_MIXED)
         return bad("precision must be PIC_FP64 or PIC_FP32_MIXED");
     if (grid->precision == PIC_FP32_MIXED &&
@@ -388,8 +394,9 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         }
         st.capacity = q.capacity;
         if (q.capacity > maxcap) maxcap = q.capacity;
-        const size_t pb = (size_t)q.capacity * sizeof(double);
-        const size_t fb4 = (size_t)q.capacity * sizeof(float);
+        // one spare slot past the end of every state array (see Parts::spare)
+        const size_t pb = (size_t)(q.capacity + 1) * sizeof(double);
+        const size_t fb4 = (size_t)(q.capacity + 1) * sizeof(float);
         for (int b = 0; b < 2 && c->precision == PIC_FP32_MIXED; ++b) {
             PartsM& P = st.bufm[b];
             if ((e = dalloc(c, (void**)&P.cell, fb4)) != hipSuccess ||
@@ -401,6 +408,7 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                 (e = dalloc(c, (void**)&P.uz, fb4)) != hipSuccess ||
                 (e = dalloc(c, (void**)&P.id, (size_t)q.capacity * sizeof(int64_t))) != hipSuccess)
                 return cfail(hip_fail(c, e, "hipMalloc particles"));
+            P.spare = (unsigned)q.capacity;
         }
         for (int b = 0; b < 2 && c->precision == PIC_FP64; ++b) {
             Parts& P = st.buf[b];
@@ -412,6 +420,7 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                 (e = dalloc(c, (void**)&P.uz, pb)) != hipSuccess ||
                 (e = dalloc(c, (void**)&P.id, (size_t)q.capacity * sizeof(int64_t))) != hipSuccess)
                 return cfail(hip_fail(c, e, "hipMalloc particles"));
+            P.spare = (unsigned)q.capacity;
         }
         if ((e = dalloc(c, (void**)&st.sc_off, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess ||
             (e = dalloc(c, (void**)&st.keys, (size_t)q.capacity * sizeof(unsigned))) != hipSuccess ||
@@ -421,6 +430,30 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     if ((e = dalloc(c, (void**)&c->far_q, (size_t)(maxcap > 0 ? maxcap : 1) * sizeof(int))) !=
         hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc far queue"));
+    if (grid->deterministic_j) {
+        // scale 2^k with 4 * (sum of capacities) * max |q w / (dt area)| * 2^k <= 2^62:
+        // no sum of hi parts can overflow
+        double bound = 0.0;
+        for (auto& st : c->sp) {
+            double jm = 0.0;
+            for (int d = 0; d < 3; ++d) jm = std::fmax(jm, std::fabs(st.c.jc[d]));
+            bound += 4.0 * (double)(st.capacity > 0 ? st.capacity : 1) * jm;
+        }
+        int k = 0;
+        if (bound > 0.0) {
+            (void)std::frexp(bound, &k);       // bound < 2^k
+            k = 62 - k;
+        }
+        if (k > 900) k = 900;
+        if (k < -900) k = -900;
+        c->det.scale = std::ldexp(1.0, k);
+        for (int d = 0; d < 3; ++d)
+            if ((e = dalloc(c, (void**)&c->det.hi[d], fb)) != hipSuccess ||
+                (e = dalloc(c, (void**)&c->det.lo[d], fb)) != hipSuccess ||
+                (e = hipMemsetAsync(c->det.hi[d], 0, fb, c->stream)) != hipSuccess ||
+                (e = hipMemsetAsync(c->det.lo[d], 0, fb, c->stream)) != hipSuccess)
+                return cfail(hip_fail(c, e, "hipMalloc deterministic J"));
+    }
     if (c->precision == PIC_FP32_MIXED)
         for (int k = 0; k < 6; ++k)
             if ((e = dalloc(c, (void**)&c->stage[k], (size_t)(maxcap > 0 ? maxcap : 1) *
@@ -568,22 +601,22 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
                     if (mixed)
                         HIPCHK(c, launch_push_mixed(c->g, s.cm, srcm, dstm, perm, keys, s.sc_off,
                                                     f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
-                                                    fn_next, c->stream));
+                                                    fn_next, c->det, c->stream));
                     else
                         HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, perm, keys, s.sc_off,
                                                       f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
-                                                      fn_next, c->stream));
+                                                      fn_next, c->det, c->stream));
                 }
                 {
                     Timed t(c, ST_FAR);
                     if (mixed)
                         HIPCHK(c, launch_far_mixed(c->g, s.cm, srcm, dstm, perm, keys, f, Jd,
                                                    c->d_err, c->d_nfar, c->far_q, fn, fn_next,
-                                                   c->stream));
+                                                   c->det, c->stream));
                     else
                         HIPCHK(c, launch_far_movers(c->g, s.c, src, dst, perm, keys, f, Jd,
                                                     c->d_err, c->d_nfar, c->far_q, fn, fn_next,
-                                                    c->stream));
+                                                    c->det, c->stream));
                 }
                 c->far_phase = 1 - c->far_phase;
                 if (c->timers) (s.pending ? c->push_perm_launches : c->push_launches)++;
@@ -597,6 +630,7 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
             }
             {
                 Timed t(c, ST_FDTD);
+                if (c->det.hi[0]) HIPCHK(c, launch_j_from_fixed(c->g.ncell, c->det, Jd, c->stream));
                 HIPCHK(c, launch_fdtd(c->g, f, fo, Jd, c->J[c->jcur], c->stream));
             }
             for (int d = 0; d < 3; ++d) {
@@ -771,7 +805,9 @@ int pic_get_counters(pic_ctx* c, int64_t out[4]) {
     out[0] = (int64_t)nfar;
     out[1] = c->rebins;
     out[2] = c->steps;
-    out[3] = c->precision == PIC_FP64 ? push_deposit_lds_bytes(c->g) : push_mixed_lds_bytes(c->g);
+    const bool det = c->det.hi[0] != nullptr;
+    out[3] = c->precision == PIC_FP64 ? push_deposit_lds_bytes(c->g, det)
+                                      : push_mixed_lds_bytes(c->g, det);
     return PIC_OK;
 }
 

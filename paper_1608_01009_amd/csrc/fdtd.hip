@@ -223,6 +223,36 @@ hipError_t launch_fdtd(const Geom& g, const Fields& f, const Fields& fo, double*
     return hipGetLastError();
 }
 
+// J from the deterministic integer accumulators, which are cleared for the
+// next step.
+__global__ void __launch_bounds__(256) j_from_fixed_kernel(int64_t n, DetJ det, double* J0,
+                                                           double* J1, double* J2) {
+#pragma clang fp contract(off)
+    const double s_hi = 1.0 / det.scale;
+    const double s_lo = s_hi / (double)(1 << kDetLoBits);
+    double* const J[3] = {J0, J1, J2};
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long h = (long long)det.hi[c][i];
+            const long long l = det.lo[c][i];
+            J[c][i] = (double)h * s_hi + (double)l * s_lo;
+            det.hi[c][i] = 0ull;
+            det.lo[c][i] = 0ll;
+        }
+    }
+}
+
+hipError_t launch_j_from_fixed(int64_t n, const DetJ& det, double* const J[3], hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(j_from_fixed_kernel, dim3((int)b), dim3(256), 0, s, n, det, J[0], J[1],
+                       J[2]);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);

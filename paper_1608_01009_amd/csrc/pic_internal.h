@@ -12,7 +12,35 @@ namespace pic {
 enum : unsigned {
     ERR_NONFINITE = 1u,   // a particle state became NaN / Inf during a step
     ERR_BADPOS = 2u,      // a loaded position is outside [0, n) or not finite
+    ERR_DETCAP = 4u,      // deterministic J: a supercell holds more than kDetMaxPerSupercell
 };
+
+// Deterministic current accumulation.  Every FP64 contribution v is split
+// exactly into two integers, hi = rint(v 2^k) and lo = rint((v 2^k - hi)
+// 2^kDetLoBits), so that v = hi 2^-k + lo 2^-(k + kDetLoBits) up to
+// 2^-(k + kDetLoBits + 1); hi and lo are summed with integer atomics (in the
+// LDS tiles: hi in 64 bits, lo in 32 bits; in global memory both in 64
+// bits), which gives the same sums in any order.  k is chosen per context
+// so that no hi sum can overflow; a supercell may hold at most
+// kDetMaxPerSupercell particles so that no LDS lo sum can overflow (a
+// particle adds at most four contributions, one per VB segment, to a node).
+constexpr int kDetLoBits = 16;
+constexpr int kDetMaxPerSupercell = 16383;
+
+struct DetJ {
+    unsigned long long* hi[3];  // global accumulators (two's complement sums)
+    long long* lo[3];
+    double scale;               // 2^k
+};
+
+__device__ __forceinline__ void det_split(double v, double scale, unsigned long long& hi, int& lo) {
+#pragma clang fp contract(off)
+    const double t = v * scale;          // exact: scale is a power of two
+    const double h = __builtin_rint(t);
+    const double r = t - h;              // exact: |r| <= 1/2 and r is t's fraction
+    hi = (unsigned long long)(long long)h;
+    lo = (int)__builtin_rint(r * (double)(1 << kDetLoBits));
+}
 
 // Geometry and constants of one context, passed by value to kernels.
 struct Geom {
@@ -43,6 +71,7 @@ struct Parts {
     double* uy;
     double* uz;
     int64_t* id;
+    unsigned spare = 0;   // index of a writable slot past the last particle (x .. uz)
 };
 
 struct Fields {
@@ -67,6 +96,7 @@ struct PartsM {
     float* uy;
     float* uz;
     int64_t* id;
+    unsigned spare = 0;   // index of a writable slot past the last particle (cell .. uz)
 };
 
 // ---- launchers (implemented in the kernel translation units) --------------
@@ -84,15 +114,18 @@ hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& s
                                const Parts& dst, const unsigned* perm, unsigned* keys,
                                const int* sc_off, const Fields& f, double* const J[3],
                                unsigned* err, unsigned long long* nfar, int* far_q,
-                               unsigned* far_n, unsigned* far_n_next, hipStream_t s);
+                               unsigned* far_n, unsigned* far_n_next, const DetJ& det,
+                               hipStream_t s);
 // The particles queued by launch_push_deposit, through global memory; clears
 // far_n_next (the counter of the next launch).
 hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src,
                              const Parts& dst, const unsigned* perm, unsigned* keys,
                              const Fields& f, double* const J[3], unsigned* err,
                              unsigned long long* nfar, int* far_q, unsigned* far_n,
-                             unsigned* far_n_next, hipStream_t s);
-int push_deposit_lds_bytes(const Geom& g);
+                             unsigned* far_n_next, const DetJ& det, hipStream_t s);
+// det.hi[0] != NULL selects the deterministic accumulation into det (J is
+// then not touched; see launch_j_from_fixed).
+int push_deposit_lds_bytes(const Geom& g, bool det);
 bool push_deposit_supported(int S, int h);
 
 // Mixed-precision counterparts of launch_push_deposit / launch_far_movers
@@ -101,13 +134,14 @@ hipError_t launch_push_mixed(const Geom& g, const SpeciesM& sp, const PartsM& sr
                              const PartsM& dst, const unsigned* perm, unsigned* keys,
                              const int* sc_off, const Fields& f, double* const J[3],
                              unsigned* err, unsigned long long* nfar, int* far_q,
-                             unsigned* far_n, unsigned* far_n_next, hipStream_t s);
+                             unsigned* far_n, unsigned* far_n_next, const DetJ& det,
+                             hipStream_t s);
 hipError_t launch_far_mixed(const Geom& g, const SpeciesM& sp, const PartsM& src,
                             const PartsM& dst, const unsigned* perm, unsigned* keys,
                             const Fields& f, double* const J[3], unsigned* err,
                             unsigned long long* nfar, int* far_q, unsigned* far_n,
-                            unsigned* far_n_next, hipStream_t s);
-int push_mixed_lds_bytes(const Geom& g);
+                            unsigned* far_n_next, const DetJ& det, hipStream_t s);
+int push_mixed_lds_bytes(const Geom& g, bool det);
 // FP64 positions / momenta (device arrays x, y, z, ux, uy, uz) -> packed
 // arrays and sort keys; ERR_BADPOS for positions outside [0, n), non-finite
 // values or momenta beyond FP32 range.
@@ -118,6 +152,10 @@ hipError_t launch_to_double(int64_t n, const PartsM& src, double* const x[6], hi
 // dst[i] = src[perm[i]] for the packed arrays and the ids
 hipError_t launch_permute_mixed(int64_t n, const unsigned* perm, const PartsM& src,
                                 const PartsM& dst, hipStream_t s);
+
+// Deterministic mode: J = hi 2^-k + lo 2^-(k + kDetLoBits) for the three
+// components, then the accumulators are cleared.
+hipError_t launch_j_from_fixed(int64_t n, const DetJ& det, double* const J[3], hipStream_t s);
 
 // Yee update from the fields f into fo (distinct arrays); also clears Jclear
 // (the buffer the next step deposits into).

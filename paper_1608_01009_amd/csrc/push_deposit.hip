@@ -78,6 +78,7 @@ struct PDArgs {
     int* far_q;          // indices of particles outside their supercell's tile
     unsigned* far_n;     // queue length for this launch
     unsigned* far_n_next;  // queue length of the next launch (cleared by far_kernel)
+    DetJ det;              // deterministic mode: integer accumulators (hi[0] == nullptr: off)
 };
 
 // Cloud-in-cell (trilinear) interpolation of one component as nested linear
@@ -488,7 +489,8 @@ __device__ __forceinline__ constexpr int jt_off(int j) {
 
 // GATHER: particle i of this step is read from src at perm[i] (the step after
 // a re-sort), otherwise at i.
-template <int S, int H, bool GATHER>
+// DET: the J tile and the flush use the exact integer split (DetJ).
+template <int S, int H, bool GATHER, bool DET>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 push_deposit_kernel(const PDArgs a) {
     using EL = EBLayout<S, H>;
@@ -500,12 +502,32 @@ push_deposit_kernel(const PDArgs a) {
     constexpr int kWaves = kBlock / 64;
     constexpr int QCAP = 28;           // queued cell-crossing particles per wave
     __shared__ double eb[6 * EL::CS];
-    __shared__ double jt[3 * JC];
+    // J tile: FP64 sums, or (DET) 64-bit hi sums followed by 32-bit lo sums
+    constexpr int JT_BYTES = DET ? 3 * JC * 12 : 3 * JC * 8;
+    __shared__ __attribute__((aligned(16))) unsigned char jraw[JT_BYTES];
+    double* const jt = (double*)jraw;
+    unsigned long long* const jth = (unsigned long long*)jraw;
+    int* const jtl = (int*)(jraw + 3 * JC * 8);
+    auto jadd = [&](int idx, double v) {
+        if (DET) {
+            unsigned long long h;
+            int l;
+            det_split(v, a.det.scale, h, l);
+            atomicAdd(&jth[idx], h);
+            atomicAdd(&jtl[idx], l);
+        } else {
+            atomicAdd(&jt[idx], v);
+        }
+    };
     __shared__ double qb[kWaves][6][QCAP];
 
     const int sc = xcd_block(blockIdx.x, gridDim.x);
     const int p0 = a.sc_off[sc], p1 = a.sc_off[sc + 1];
     if (p0 >= p1) return;  // empty supercell: uniform exit before any barrier
+    if (DET && p1 - p0 > kDetMaxPerSupercell) {
+        if (threadIdx.x == 0) atomicOr(a.err, ERR_DETCAP);
+        return;
+    }
 
     const Geom& g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -528,7 +550,7 @@ push_deposit_kernel(const PDArgs a) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = a.EB[c][gi];
     }
-    for (int t = threadIdx.x; t < 3 * JC; t += kBlock) jt[t] = 0.0;
+    for (int t = threadIdx.x; t < JT_BYTES / 4; t += kBlock) ((int*)jraw)[t] = 0;
     __syncthreads();
 
     const double L[3] = {(double)nx, (double)ny, (double)nz};
@@ -561,7 +583,7 @@ push_deposit_kernel(const PDArgs a) {
         const int jo0 = rel[0] + H + 1 - c0[0], jo1 = rel[1] + H + 1 - c0[1],
                   jo2 = rel[2] + H + 1 - c0[2];
         vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double v) {
-            atomicAdd(&jt[d * JC + (i + jo0) + PY * (j + jo1) + PZ * (k + jo2)], v);
+            jadd(d * JC + (i + jo0) + PY * (j + jo1) + PZ * (k + jo2), v);
         });
     };
     // queued crossers of this wave: one per lane, then the queue is empty
@@ -610,6 +632,13 @@ push_deposit_kernel(const PDArgs a) {
         }
         bool crosser = false, far = false;
         double x1[3] = {0.0, 0.0, 0.0};
+        // Every lane stores; lanes without a pushed particle (past the end
+        // of the supercell, far movers, whose slot far_kernel rewrites, and
+        // non-finite states) store to the spare slot.  The stores then sit on
+        // every path of the loop body, so the wait for the next particle's
+        // prefetched loads does not also wait for this particle's stores.
+        unsigned o = a.dst.spare;
+        double xw[3] = {0.0, 0.0, 0.0};
         if (valid) {
             // stored positions lie in [0, L) (this also rejects NaN); a
             // non-finite momentum shows up in the pushed state checked below
@@ -648,24 +677,26 @@ push_deposit_kernel(const PDArgs a) {
                     const int key =
                         (rel[0] + H + 1) + PY * (rel[1] + H + 1) + PZ * (rel[2] + H + 1);
                     vb_single(x0, x1, c0, a.sp.jc, [&](int j, double v) {
-                        atomicAdd(&jt[key + jt_off<PY, PZ, JC>(j)], v);
+                        jadd(key + jt_off<PY, PZ, JC>(j), v);
                     });
                 } else {
                     crosser = true;
                 }
                 // positions are stored wrapped into [0, n)
-                double xw[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) xw[d] = wrap_coord(x1[d], L[d]);
-                const unsigned b = (unsigned)ip * 8u;
-                *(double*)((char*)a.dst.x + b) = xw[0];
-                *(double*)((char*)a.dst.y + b) = xw[1];
-                *(double*)((char*)a.dst.z + b) = xw[2];
-                *(double*)((char*)a.dst.ux + b) = u[0];
-                *(double*)((char*)a.dst.uy + b) = u[1];
-                *(double*)((char*)a.dst.uz + b) = u[2];
-                if (a.keys) a.keys[ip] = sort_key<S>(g, xw);
+                o = (unsigned)ip;
             }
+        }
+        {
+            const unsigned b = o * 8u;
+            *(double*)((char*)a.dst.x + b) = xw[0];
+            *(double*)((char*)a.dst.y + b) = xw[1];
+            *(double*)((char*)a.dst.z + b) = xw[2];
+            *(double*)((char*)a.dst.ux + b) = u[0];
+            *(double*)((char*)a.dst.uy + b) = u[1];
+            *(double*)((char*)a.dst.uz + b) = u[2];
+            if (a.keys && o != a.dst.spare) a.keys[o] = sort_key<S>(g, xw);
         }
 
         // Far movers (outside the tile window) are left untouched here and
@@ -713,12 +744,27 @@ push_deposit_kernel(const PDArgs a) {
     for (int r = threadIdx.x; r < TJ3; r += kBlock) {
         const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
         const int li = tx + PY * ty + PZ * tz;
-        const double v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
-        if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) {
-            const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+        if (DET) {
+            const unsigned long long h[3] = {jth[li], jth[JC + li], jth[2 * JC + li]};
+            const int l[3] = {jtl[li], jtl[JC + li], jtl[2 * JC + li]};
+            if ((h[0] | h[1] | h[2]) != 0ull || (l[0] | l[1] | l[2]) != 0) {
+                const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (v[c] != 0.0) unsafeAtomicAdd(&a.J[c][gi], v[c]);
+                for (int c = 0; c < 3; ++c) {
+                    if (h[c] != 0ull) atomicAdd(&a.det.hi[c][gi], h[c]);
+                    if (l[c] != 0)
+                        atomicAdd((unsigned long long*)&a.det.lo[c][gi],
+                                  (unsigned long long)(long long)l[c]);
+                }
+            }
+        } else {
+            const double v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
+            if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) {
+                const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (v[c] != 0.0) unsafeAtomicAdd(&a.J[c][gi], v[c]);
+            }
         }
     }
 }
@@ -763,7 +809,16 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
         vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double vv) {
-            unsafeAtomicAdd(&a.J[d][wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz))], vv);
+            const int gi = wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz));
+            if (a.det.hi[0]) {
+                unsigned long long h;
+                int l;
+                det_split(vv, a.det.scale, h, l);
+                atomicAdd(&a.det.hi[d][gi], h);
+                atomicAdd((unsigned long long*)&a.det.lo[d][gi], (unsigned long long)(long long)l);
+            } else {
+                unsafeAtomicAdd(&a.J[d][gi], vv);
+            }
         });
         const double xw[3] = {wrap_coord(x1[0], L[0]), wrap_coord(x1[1], L[1]),
                               wrap_coord(x1[2], L[2])};
@@ -781,20 +836,26 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
 
 template <int S, int H>
 hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
-    if (args.perm)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, true>), dim3(args.g.nsc), dim3(kBlock), 0, s,
-                           args);
+    const bool det = args.det.hi[0] != nullptr;
+    if (args.perm && det)
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, true>), dim3(args.g.nsc), dim3(kBlock),
+                           0, s, args);
+    else if (args.perm)
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, args);
+    else if (det)
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, true>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, args);
     else
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, false>), dim3(args.g.nsc), dim3(kBlock), 0,
-                           s, args);
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
 
 template <int S, int H>
-constexpr int lds_bytes_sh() {
-    return (6 * EBLayout<S, H>::CS + 3 * JLayout<S, H>::JC +
-            (kBlock / 64) * 6 * 28) *
-           (int)sizeof(double);
+constexpr int lds_bytes_sh(bool det) {
+    return (6 * EBLayout<S, H>::CS + (kBlock / 64) * 6 * 28) * (int)sizeof(double) +
+           3 * JLayout<S, H>::JC * (det ? 12 : 8);
 }
 
 }  // namespace
@@ -811,8 +872,8 @@ bool push_deposit_supported(int S, int h) {
     return false;
 }
 
-int push_deposit_lds_bytes(const Geom& g) {
-#define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return lds_bytes_sh<s_, h_>();
+int push_deposit_lds_bytes(const Geom& g, bool det) {
+#define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return lds_bytes_sh<s_, h_>(det);
     PIC_SH_TABLE(PIC_X)
 #undef PIC_X
     return -1;
@@ -823,8 +884,9 @@ namespace {
 PDArgs make_args(const Geom& g, const SpeciesC& sp, const Parts& src, const Parts& dst,
                  const unsigned* perm, unsigned* keys, const int* sc_off, const Fields& f,
                  double* const J[3], unsigned* err, unsigned long long* nfar, int* far_q,
-                 unsigned* far_n, unsigned* far_n_next) {
+                 unsigned* far_n, unsigned* far_n_next, const DetJ& det) {
     PDArgs args;
+    args.det = det;
     args.g = g;
     args.sp = sp;
     args.src = src;
@@ -851,9 +913,10 @@ hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& s
                                const Parts& dst, const unsigned* perm, unsigned* keys,
                                const int* sc_off, const Fields& f, double* const J[3],
                                unsigned* err, unsigned long long* nfar, int* far_q,
-                               unsigned* far_n, unsigned* far_n_next, hipStream_t s) {
+                               unsigned* far_n, unsigned* far_n_next, const DetJ& det,
+                               hipStream_t s) {
     const PDArgs args = make_args(g, sp, src, dst, perm, keys, sc_off, f, J, err, nfar, far_q,
-                                  far_n, far_n_next);
+                                  far_n, far_n_next, det);
     if (g.nsc <= 0) return hipSuccess;
 #define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return launch_sh<s_, h_>(args, s);
     PIC_SH_TABLE(PIC_X)
@@ -865,9 +928,9 @@ hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src
                              const Parts& dst, const unsigned* perm, unsigned* keys,
                              const Fields& f, double* const J[3], unsigned* err,
                              unsigned long long* nfar, int* far_q, unsigned* far_n,
-                             unsigned* far_n_next, hipStream_t s) {
+                             unsigned* far_n_next, const DetJ& det, hipStream_t s) {
     const PDArgs args = make_args(g, sp, src, dst, perm, keys, nullptr, f, J, err, nfar, far_q,
-                                  far_n, far_n_next);
+                                  far_n, far_n_next, det);
     hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }

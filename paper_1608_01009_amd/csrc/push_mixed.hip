@@ -6,7 +6,7 @@
 //   - the gather from an FP32 copy of the E/B tile, Boris, advance and the VB
 //     split and weights in FP32, in cell-local coordinates;
 //   - each FP32 contribution converted (exactly) to FP64 and summed in an FP64
-//     LDS J tile (ds_add_f64: on gfx950 the FP32 LDS atomic add serializes
+//     (or, in the deterministic mode, exact integer) LDS J tile (ds_add_f64: on gfx950 the FP32 LDS atomic add serializes
 //     over the lanes, ~20x the cost of the FP64 one), then added into the
 //     FP64 global J.
 // This is an extension beyond the paper, which computes in double precision
@@ -72,6 +72,7 @@ struct MArgs {
     int* far_q;
     unsigned* far_n;
     unsigned* far_n_next;
+    DetJ det;               // deterministic mode (hi[0] == nullptr: off)
 };
 
 // LDS layouts: FP32 E/B tile, node (tx, ty, tz) of component c at
@@ -401,7 +402,7 @@ __device__ __forceinline__ bool finite3f(float a, float b, float c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-template <int S, int H, bool GATHER>
+template <int S, int H, bool GATHER, bool DET>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6)))
 push_mixed_kernel(const MArgs a) {
     using L = MLayout<S, H>;
@@ -411,13 +412,33 @@ push_mixed_kernel(const MArgs a) {
     constexpr int kWaves = kBlock / 64;
     constexpr int QCAP = 28;
     __shared__ float eb[6 * L::ECS];
-    __shared__ double jt[3 * JC];
+    // J tile: FP64 sums, or (DET) 64-bit hi sums followed by 32-bit lo sums
+    constexpr int JT_BYTES = DET ? 3 * JC * 12 : 3 * JC * 8;
+    __shared__ __attribute__((aligned(16))) unsigned char jraw[JT_BYTES];
+    double* const jt = (double*)jraw;
+    unsigned long long* const jth = (unsigned long long*)jraw;
+    int* const jtl = (int*)(jraw + 3 * JC * 8);
+    auto jadd = [&](int idx, double v) {
+        if (DET) {
+            unsigned long long h;
+            int l;
+            det_split(v, a.det.scale, h, l);
+            atomicAdd(&jth[idx], h);
+            atomicAdd(&jtl[idx], l);
+        } else {
+            atomicAdd(&jt[idx], v);
+        }
+    };
     __shared__ float qb[kWaves][6][QCAP];
     __shared__ int qk[kWaves][QCAP];
 
     const int sc = xcd_block(blockIdx.x, gridDim.x);
     const int p0 = a.sc_off[sc], p1 = a.sc_off[sc + 1];
     if (p0 >= p1) return;
+    if (DET && p1 - p0 > kDetMaxPerSupercell) {
+        if (threadIdx.x == 0) atomicOr(a.err, ERR_DETCAP);
+        return;
+    }
 
     const Geom& g = a.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -439,7 +460,7 @@ push_mixed_kernel(const MArgs a) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) eb[c * L::ECS + li] = (float)a.EB[c][gi];
     }
-    for (int t = threadIdx.x; t < 3 * JC; t += kBlock) jt[t] = 0.0;
+    for (int t = threadIdx.x; t < JT_BYTES / 4; t += kBlock) ((int*)jraw)[t] = 0;
     __syncthreads();
 
     // relative cell of c inside the tile window [-H, S+H), periodic
@@ -460,7 +481,7 @@ push_mixed_kernel(const MArgs a) {
     // general move of a particle whose start cell sits at tile key `key`
     auto deposit_tile = [&](int key, const float o0[3], const float o1[3]) {
         vb_move_m(o0, o1, a.sp.jc, [&](int d, int rx, int ry, int rz, float v) {
-            atomicAdd(&jt[d * JC + key + rx + JPY * ry + JPZ * rz], (double)v);
+            jadd(d * JC + key + rx + JPY * ry + JPZ * rz, (double)v);
         });
     };
     auto drain = [&](int cnt) {
@@ -508,6 +529,11 @@ push_mixed_kernel(const MArgs a) {
         bool crosser = false, far = false;
         float o1[3] = {0.f, 0.f, 0.f};
         int key = 0;
+        // every lane stores (see push_deposit_kernel): lanes without a pushed
+        // particle store to the spare slot
+        unsigned o = a.dst.spare;
+        int cn[3] = {0, 0, 0};
+        float on[3] = {0.f, 0.f, 0.f};
         if (valid) {
             int c[3], rel[3];
             unpack_cell(cp, c);
@@ -533,24 +559,25 @@ push_mixed_kernel(const MArgs a) {
                                     floorf(o1[2]) == 0.0f;
                 if (single) {
                     vb_single_m(o0, o1, a.sp.jc, [&](int j, float v) {
-                        atomicAdd(&jt[key + jt_off_m<JPY, JPZ, JC>(j)], (double)v);
+                        jadd(key + jt_off_m<JPY, JPZ, JC>(j), (double)v);
                     });
                 } else {
                     crosser = true;
                 }
-                int cn[3];
-                float on[3];
                 cell_update(c, o1, nn, cn, on);
-                const unsigned b = (unsigned)ip * 4u;
-                *(unsigned*)((char*)a.dst.cell + b) = pack_cell(cn[0], cn[1], cn[2]);
-                *(float*)((char*)a.dst.ox + b) = on[0];
-                *(float*)((char*)a.dst.oy + b) = on[1];
-                *(float*)((char*)a.dst.oz + b) = on[2];
-                *(float*)((char*)a.dst.ux + b) = u[0];
-                *(float*)((char*)a.dst.uy + b) = u[1];
-                *(float*)((char*)a.dst.uz + b) = u[2];
-                if (a.keys) a.keys[ip] = sort_key_m<S>(g, cn);
+                o = (unsigned)ip;
             }
+        }
+        {
+            const unsigned b = o * 4u;
+            *(unsigned*)((char*)a.dst.cell + b) = pack_cell(cn[0], cn[1], cn[2]);
+            *(float*)((char*)a.dst.ox + b) = on[0];
+            *(float*)((char*)a.dst.oy + b) = on[1];
+            *(float*)((char*)a.dst.oz + b) = on[2];
+            *(float*)((char*)a.dst.ux + b) = u[0];
+            *(float*)((char*)a.dst.uy + b) = u[1];
+            *(float*)((char*)a.dst.uz + b) = u[2];
+            if (a.keys && o != a.dst.spare) a.keys[o] = sort_key_m<S>(g, cn);
         }
         {
             const unsigned long long fm = __ballot(far);
@@ -593,12 +620,27 @@ push_mixed_kernel(const MArgs a) {
     for (int r = threadIdx.x; r < TJ3; r += kBlock) {
         const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
         const int li = tx + JPY * ty + JPZ * tz;
-        const double v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
-        if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) {
-            const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+        if (DET) {
+            const unsigned long long h[3] = {jth[li], jth[JC + li], jth[2 * JC + li]};
+            const int l[3] = {jtl[li], jtl[JC + li], jtl[2 * JC + li]};
+            if ((h[0] | h[1] | h[2]) != 0ull || (l[0] | l[1] | l[2]) != 0) {
+                const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (v[c] != 0.0) unsafeAtomicAdd(&a.J[c][gi], v[c]);
+                for (int c = 0; c < 3; ++c) {
+                    if (h[c] != 0ull) atomicAdd(&a.det.hi[c][gi], h[c]);
+                    if (l[c] != 0)
+                        atomicAdd((unsigned long long*)&a.det.lo[c][gi],
+                                  (unsigned long long)(long long)l[c]);
+                }
+            }
+        } else {
+            const double v[3] = {jt[li], jt[JC + li], jt[2 * JC + li]};
+            if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) {
+                const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (v[c] != 0.0) unsafeAtomicAdd(&a.J[c][gi], v[c]);
+            }
         }
     }
 }
@@ -630,7 +672,15 @@ __global__ void __launch_bounds__(kBlock) far_mixed_kernel(const MArgs a) {
         vb_move_m(o0, o1, a.sp.jc, [&](int d, int rx, int ry, int rz, float v) {
             const int gi = wrapi(c[0] + rx, nn[0]) +
                            nn[0] * (wrapi(c[1] + ry, nn[1]) + nn[1] * wrapi(c[2] + rz, nn[2]));
-            unsafeAtomicAdd(&a.J[d][gi], (double)v);
+            if (a.det.hi[0]) {
+                unsigned long long h;
+                int l;
+                det_split((double)v, a.det.scale, h, l);
+                atomicAdd(&a.det.hi[d][gi], h);
+                atomicAdd((unsigned long long*)&a.det.lo[d][gi], (unsigned long long)(long long)l);
+            } else {
+                unsafeAtomicAdd(&a.J[d][gi], (double)v);
+            }
         });
         int cn[3];
         float on[3];
@@ -727,26 +777,31 @@ int grid256(int64_t n) {
 
 template <int S, int H>
 hipError_t launch_m(const MArgs& args, hipStream_t s) {
-    if (args.perm)
-        hipLaunchKernelGGL((push_mixed_kernel<S, H, true>), dim3(args.g.nsc), dim3(kBlock), 0, s,
-                           args);
+    const bool det = args.det.hi[0] != nullptr;
+    const dim3 grid(args.g.nsc), block(kBlock);
+    if (args.perm && det)
+        hipLaunchKernelGGL((push_mixed_kernel<S, H, true, true>), grid, block, 0, s, args);
+    else if (args.perm)
+        hipLaunchKernelGGL((push_mixed_kernel<S, H, true, false>), grid, block, 0, s, args);
+    else if (det)
+        hipLaunchKernelGGL((push_mixed_kernel<S, H, false, true>), grid, block, 0, s, args);
     else
-        hipLaunchKernelGGL((push_mixed_kernel<S, H, false>), dim3(args.g.nsc), dim3(kBlock), 0, s,
-                           args);
+        hipLaunchKernelGGL((push_mixed_kernel<S, H, false, false>), grid, block, 0, s, args);
     return hipGetLastError();
 }
 
 template <int S, int H>
-constexpr int lds_bytes_m() {
-    return 6 * MLayout<S, H>::ECS * (int)sizeof(float) +
-           3 * MLayout<S, H>::JC * (int)sizeof(double) + (kBlock / 64) * 7 * 28 * 4;
+constexpr int lds_bytes_m(bool det) {
+    return 6 * MLayout<S, H>::ECS * (int)sizeof(float) + 3 * MLayout<S, H>::JC * (det ? 12 : 8) +
+           (kBlock / 64) * 7 * 28 * 4;
 }
 
 MArgs make_margs(const Geom& g, const SpeciesM& sp, const PartsM& src, const PartsM& dst,
                  const unsigned* perm, unsigned* keys, const int* sc_off, const Fields& f,
                  double* const J[3], unsigned* err, unsigned long long* nfar, int* far_q,
-                 unsigned* far_n, unsigned* far_n_next) {
+                 unsigned* far_n, unsigned* far_n_next, const DetJ& det) {
     MArgs a;
+    a.det = det;
     a.g = g;
     a.sp = sp;
     a.src = src;
@@ -772,8 +827,8 @@ MArgs make_margs(const Geom& g, const SpeciesM& sp, const PartsM& src, const Par
 #define PIC_SH_TABLE_M(X) \
     X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 1) X(4, 1) X(4, 2) X(5, 1) X(6, 1)
 
-int push_mixed_lds_bytes(const Geom& g) {
-#define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return lds_bytes_m<s_, h_>();
+int push_mixed_lds_bytes(const Geom& g, bool det) {
+#define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return lds_bytes_m<s_, h_>(det);
     PIC_SH_TABLE_M(PIC_X)
 #undef PIC_X
     return -1;
@@ -783,9 +838,10 @@ hipError_t launch_push_mixed(const Geom& g, const SpeciesM& sp, const PartsM& sr
                              const PartsM& dst, const unsigned* perm, unsigned* keys,
                              const int* sc_off, const Fields& f, double* const J[3],
                              unsigned* err, unsigned long long* nfar, int* far_q,
-                             unsigned* far_n, unsigned* far_n_next, hipStream_t s) {
+                             unsigned* far_n, unsigned* far_n_next, const DetJ& det,
+                             hipStream_t s) {
     const MArgs args = make_margs(g, sp, src, dst, perm, keys, sc_off, f, J, err, nfar, far_q,
-                                  far_n, far_n_next);
+                                  far_n, far_n_next, det);
     if (g.nsc <= 0) return hipSuccess;
 #define PIC_X(s_, h_) if (g.S == s_ && g.h == h_) return launch_m<s_, h_>(args, s);
     PIC_SH_TABLE_M(PIC_X)
@@ -797,9 +853,9 @@ hipError_t launch_far_mixed(const Geom& g, const SpeciesM& sp, const PartsM& src
                             const PartsM& dst, const unsigned* perm, unsigned* keys,
                             const Fields& f, double* const J[3], unsigned* err,
                             unsigned long long* nfar, int* far_q, unsigned* far_n,
-                            unsigned* far_n_next, hipStream_t s) {
+                            unsigned* far_n_next, const DetJ& det, hipStream_t s) {
     const MArgs args = make_margs(g, sp, src, dst, perm, keys, nullptr, f, J, err, nfar, far_q,
-                                  far_n, far_n_next);
+                                  far_n, far_n_next, det);
     hipLaunchKernelGGL(far_mixed_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }

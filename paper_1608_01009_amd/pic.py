@@ -41,8 +41,8 @@ ABI_SYMBOLS = ("pic_create", "pic_load_particles", "pic_set_fields", "pic_step",
 
 class PicGrid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("supercell", C.c_int32), ("rebin_every", C.c_int32),
-                ("halo", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32 * 3),
-                ("stream", C.c_void_p)]
+                ("halo", C.c_int32), ("precision", C.c_int32), ("deterministic_j", C.c_int32),
+                ("reserved", C.c_int32 * 2), ("stream", C.c_void_p)]
 
 
 class PicSpecies(C.Structure):
@@ -131,11 +131,13 @@ def _torch_stream():
 
 
 def pic_create(n: Sequence[int], dx: Sequence[float], dt: float, species, *, supercell: int = 4,
-               rebin_every: int = 20, halo: int = 0, stream=None, precision="fp64"):
+               rebin_every: int = 20, halo: int = 0, stream=None, precision="fp64",
+               deterministic_j: bool = False):
     """``species``: sequence of ``(charge, mass, weight, capacity)``.
     ``stream``: None (library-owned stream), ``"torch"`` (torch's current
     stream) or a raw ``hipStream_t`` integer.  ``precision``: "fp64" or
-    "mixed" (PIC_FP32_MIXED).  Returns the context handle."""
+    "mixed" (PIC_FP32_MIXED).  ``deterministic_j``: bit-reproducible current
+    accumulation.  Returns the context handle."""
     L = library()
     g = PicGrid()
     for d in range(3):
@@ -144,6 +146,7 @@ def pic_create(n: Sequence[int], dx: Sequence[float], dt: float, species, *, sup
     g.rebin_every = int(rebin_every)
     g.halo = int(halo)
     g.precision = _PRECISION[precision] if precision in _PRECISION else int(precision)
+    g.deterministic_j = int(deterministic_j)
     if stream == "torch":
         stream = _torch_stream()
     g.stream = stream
@@ -247,13 +250,14 @@ class Simulation:
     """Owning convenience wrapper around one context."""
 
     def __init__(self, n, dx, dt, species, *, supercell=4, rebin_every=20, halo=0, stream=None,
-                 precision="fp64"):
+                 precision="fp64", deterministic_j=False):
         self.n = tuple(int(v) for v in n)
         self.ncell = self.n[0] * self.n[1] * self.n[2]
         self.species = [tuple(s) for s in species]
         self.precision = precision
         self.ctx = pic_create(n, dx, dt, species, supercell=supercell, rebin_every=rebin_every,
-                              halo=halo, stream=stream, precision=precision)
+                              halo=halo, stream=stream, precision=precision,
+                              deterministic_j=deterministic_j)
 
     @classmethod
     def from_workload(cls, wl, capacity_factor=1.0, **kw):
