@@ -34,6 +34,8 @@ METRIC = "particle updates/s (gather+push+deposit) FP64 vs FP32-mixed; % HBM roo
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "push_deposit_64c_50ppc_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_01009_amd", "csrc", "push_deposit.hip")
+COUNTERS_MIXED = os.path.join(ROOT, "profiles", "push_mixed_64c_50ppc_counters.md")
+KERNEL_SRC_MIXED = os.path.join(ROOT, "paper_1608_01009_amd", "csrc", "push_mixed.hip")
 
 
 def log(*a):
@@ -49,19 +51,19 @@ def algorithmic_bytes_per_launch(nparticles: int, ncell: int, precision: str = "
     return nparticles * per_particle + ncell * 72
 
 
-def measured_traffic():
+def measured_traffic(counters=COUNTERS, kernel_src=KERNEL_SRC):
     """HBM bytes per push+deposit launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
     if it was taken on the current kernel source; otherwise None."""
-    if not os.path.exists(COUNTERS):
+    if not os.path.exists(counters):
         return None
     try:
         fields = {}
-        for line in open(COUNTERS):
+        for line in open(counters):
             if ":" in line and not line.startswith((" ", "#", "|")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        src_hash = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
         if fields.get("kernel_source_sha256") != src_hash:
             return None
         return float(fields["hbm_bytes_per_launch"])
@@ -112,9 +114,10 @@ def mixed_leg(wl, args):
         f"{push_ms_avg*1e3:.1f} us/launch; gauss drift {d[4]:.3e}")
     return {"value": n * args.steps / wall, "unit": "particle updates/s",
             "ms_per_step": wall * 1e3 / args.steps, "dtype": "f32 (FP64 fields and J)",
-            "roofline": {"bound": "hbm", "kernel": "push_mixed_kernel<4, 1, false>",
+            "roofline": {"bound": "hbm", "kernel": "push_mixed_kernel<4, 1, false, false>",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(COUNTERS_MIXED, KERNEL_SRC_MIXED),
                          "algorithmic_bytes_per_launch": bytes_launch,
                          "avg_launch_us": push_ms_avg * 1e3},
             "gauss_drift": d[4]}
@@ -203,7 +206,7 @@ def main():
                                "push_deposit_after_resort": ts[2] / ts[8],
                                "far_movers": ts[4] / ts[8], "fdtd": ts[5] / ts[8],
                                "resort": ts[6] / ts[8], "total": ts[7] / ts[8]},
-        "roofline": {"bound": "hbm", "kernel": "push_deposit_kernel<4, 1, false>",
+        "roofline": {"bound": "hbm", "kernel": "push_deposit_kernel<4, 1, false, false>",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch,
