@@ -62,6 +62,10 @@ def lib():
         L.orc_push_deposit_mixed.argtypes = [G, C.c_double, C.c_double, C.c_double, C.c_int64,
                                              _D, _D, _D, _D, _D, _D, PP6, PP3, C.c_void_p,
                                              C.c_void_p]
+        L.orc_fdtd_adjoint.argtypes = [G, PP3, PP3, PP3]
+        L.orc_adjoint_particles.argtypes = [G, C.c_double, C.c_double, C.c_double, C.c_int64,
+                                            _D, _D, _D, _D, _D, _D, PP6, PP3,
+                                            _D, _D, _D, _D, _D, _D, PP6]
         L.orc_rho.argtypes = [G, C.c_double, C.c_double, C.c_int64, _D, _D, _D, _D]
         L.orc_gauss.argtypes = [G, PP3, _D, _D]
         L.orc_divb.argtypes = [G, PP3, _D]
@@ -162,6 +166,23 @@ def divb(g: OrcGrid, B):
     out = np.zeros_like(B[0])
     lib().orc_divb(C.byref(g), _ptrs(B), _dp(out))
     return out
+
+
+def fdtd_adjoint(g: OrcGrid, lE, lB):
+    """Transposed Yee update in place on (lE, lB); returns lJ."""
+    nc = len(lE[0])
+    lJ = [np.zeros(nc) for _ in range(3)]
+    lib().orc_fdtd_adjoint(C.byref(g), _ptrs(lE), _ptrs(lB), _ptrs(lJ))
+    return lJ
+
+
+def adjoint_particles(g: OrcGrid, q, m, w, state, EB, lJ, lam, lEB):
+    """One species' particle loop reversed.  state: x, y, z, ux, uy, uz at the
+    start of the step; lam: six adjoint arrays, end of step -> start of step
+    (in place); lEB: six arrays, accumulated."""
+    n = len(state[0])
+    lib().orc_adjoint_particles(C.byref(g), q, m, w, n, *[_dp(a) for a in state[:6]],
+                                _ptrs(EB), _ptrs(lJ), *[_dp(a) for a in lam], _ptrs(lEB))
 
 
 def mixed_round_pos(x, n):
@@ -293,6 +314,55 @@ class OracleSim:
                     if self.P[s] is not None:
                         self._sort(s)
                 self.steps_since_sort = 0
+
+    def run_recorded(self, nsteps):
+        """Advance ``nsteps`` steps (FP64 only), keeping the full state at the
+        start of every step: a tape for :meth:`adjoint`."""
+        assert self.precision == "fp64"
+        tape = []
+        for _ in range(int(nsteps)):
+            tape.append(([None if P is None else [a.copy() for a in P] for P in self.P],
+                         [f.copy() for f in self.F[:6]]))
+            self.step(1)
+        return tape
+
+    def adjoint(self, tape, seed_EB, seed_P):
+        """Reverse-mode gradient of a scalar of the current state with respect
+        to the state at the start of ``tape``.  ``seed_EB``: six arrays (dL/dE,
+        dL/dB now); ``seed_P``: per species six arrays (dL/dx .. dL/duz, stored
+        order now) or None.  Returns (six field gradients, per species six
+        gradient arrays in the stored order at the start of the tape).  A
+        re-sort only reorders particles: its transpose moves each adjoint back
+        to the slot of the same particle id."""
+        lEB = [np.array(a, dtype=np.float64).copy() for a in seed_EB]
+        lam = []
+        for s, P in enumerate(self.P):
+            if P is None:
+                lam.append(None)
+                continue
+            sd = None if seed_P is None else seed_P[s]
+            lam.append([np.zeros(len(P[0])) if sd is None else np.array(sd[k], dtype=np.float64).copy()
+                        for k in range(6)])
+        ids_after = [None if P is None else P[6] for P in self.P]
+        for j in range(len(tape) - 1, -1, -1):
+            Pj, EBj = tape[j]
+            for s, P in enumerate(Pj):
+                if P is None:
+                    continue
+                if not np.array_equal(P[6], ids_after[s]):
+                    order = np.argsort(P[6], kind="stable")
+                    slot = order[np.searchsorted(P[6][order], ids_after[s])]
+                    for k in range(6):
+                        moved = np.empty_like(lam[s][k])
+                        moved[slot] = lam[s][k]
+                        lam[s][k] = moved
+            lJ = fdtd_adjoint(self.g, lEB[0:3], lEB[3:6])
+            for s, (q, m, w) in enumerate(self.species):
+                if Pj[s] is None or len(Pj[s][0]) == 0:
+                    continue
+                adjoint_particles(self.g, q, m, w, Pj[s], EBj, lJ, lam[s], lEB)
+            ids_after = [None if P is None else P[6] for P in Pj]
+        return lEB, lam
 
     def fields(self):
         return {k: self.F[i] for i, k in enumerate(FIELD_NAMES)}

@@ -90,6 +90,22 @@ void orc_push_deposit_mixed(const orc_grid* g, double q, double m, double w, int
                             double* uz, const double* const EB[6], double* const J[3],
                             double* const* Jabs, int64_t* const* Jcnt);
 
+/* Adjoint of one step (pic_oracle_adjoint.c).  orc_fdtd_adjoint: given the
+ * adjoint (lE, lB) of the fields after orc_fdtd, overwrite it with the adjoint
+ * of the fields before and write lJ, the adjoint of the current.
+ * orc_adjoint_particles: one species' particle loop reversed, from its state
+ * (x, u) and the fields at the start of the step; lx..luz hold the adjoint of
+ * the state after the step on entry and before it on return; lEB accumulates
+ * the adjoint of the interpolated fields. */
+void orc_fdtd_adjoint(const orc_grid* g, double* const lE[3], double* const lB[3],
+                      double* const lJ[3]);
+void orc_adjoint_particles(const orc_grid* g, double q, double m, double w, int64_t n,
+                           const double* x, const double* y, const double* z,
+                           const double* ux, const double* uy, const double* uz,
+                           const double* const EB[6], const double* const lJ[3],
+                           double* lx, double* ly, double* lz, double* lux, double* luy,
+                           double* luz, double* const lEB[6]);
+
 /* CIC charge density at the nodes: rho += q w W(x-i)W(y-j)W(z-k) / dV. */
 void orc_rho(const orc_grid* g, double q, double w, int64_t n,
              const double* x, const double* y, const double* z, double* rho);
