@@ -123,6 +123,39 @@ def mixed_leg(wl, args):
             "gauss_drift": d[4]}
 
 
+def adjoint_leg():
+    """Gradient of the final field energy through 400 recorded steps of the
+    32^3 / 16 ppc eight-mode workload (deterministic J, checkpoints every 20
+    steps): the recorded forward run and the reverse sweep, timed apart."""
+    from paper_1608_01009_amd import pic
+    from paper_1608_01009_amd import workloads as W
+    import torch
+    wl = W.config5()
+    sp = wl.species[0]
+    sim = pic.Simulation(wl.n, wl.dx, wl.dt, [(sp.charge, sp.mass, sp.weight, sp.n)],
+                         supercell=wl.S, rebin_every=wl.R, deterministic_j=True)
+    sim.load_particles(0, *sp.arrays())
+    sim.set_fields(wl.fields)
+    log(f"adjoint: {wl.name}, {wl.steps} recorded steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.record(20)
+    sim.step(wl.steps)
+    t1 = time.perf_counter()
+    F = sim.fields()
+    seed = [F[c].copy() for c in range(6)]
+    t2 = time.perf_counter()
+    gF, _ = sim.backward(seed, None)
+    t3 = time.perf_counter()
+    sim.close()
+    fwd, bwd = (t1 - t0) * 1e3 / wl.steps, (t3 - t2) * 1e3 / wl.steps
+    log(f"adjoint: forward {fwd:.3f} ms/step recorded, backward {bwd:.3f} ms/step")
+    return {"workload": wl.name, "particles": sp.n, "steps": wl.steps, "checkpoint_every": 20,
+            "loss": "final field energy", "forward_recorded_ms_per_step": fwd,
+            "backward_ms_per_step": bwd,
+            "backward_particle_updates_per_s": sp.n * wl.steps / (t3 - t2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-mixed leg (same workload, PIC_FP32_MIXED)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint leg (gradient through 400 recorded steps)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -215,6 +250,8 @@ def main():
     }
     if not args.no_mixed:
         rec["fp32_mixed"] = mixed_leg(wl, args)
+    if not args.no_adjoint:
+        rec["adjoint"] = adjoint_leg()
     if args.copy_calibration_mib > 0:
         nel = args.copy_calibration_mib * (1 << 20) // 8
         a = torch.ones(nel, dtype=torch.float64, device="cuda")

@@ -172,6 +172,51 @@ int pic_get_timers(pic_ctx* ctx, double ms[10]);
  * out[3] LDS bytes per push+deposit workgroup. */
 int pic_get_counters(pic_ctx* ctx, int64_t out[4]);
 
+/* ---- Adjoint (reverse-mode gradient through the step), PIC_FP64 only ----
+ *
+ * The paper defines the forward step (Section 2: Maxwell integration, field
+ * interpolation, equations of motion, current deposition; Section 3: CIC form
+ * factor, Villasenor-Buneman deposition); these calls differentiate that
+ * step.  The gradient of a scalar L of the current state is carried back to
+ * the state at the start of a recorded run:
+ *   fields: the transposed Yee update (the curls' transposes, J's -dt);
+ *   particles: the vector-Jacobian product of gather, Boris push, advance and
+ *     VB deposit (one-sided where a CIC weight or a cell crossing has a kink
+ *     at a cell plane), with the transposed interpolation summed with FP64
+ *     atomics;
+ *   re-sort: each particle's adjoint moves back to its slot before the sort.
+ * The forward state of every step is recomputed from checkpoints taken every
+ * `checkpoint_every` steps during the recorded run, one segment at a time
+ * (memory: one checkpoint per segment, each the particles with ids, E, B and
+ * J; plus, during pic_backward, the state of every step of one segment).
+ * With deterministic_j the recomputed steps equal the recorded ones bit for
+ * bit; with atomic J they may differ by rounding, and the gradient is that of
+ * the recomputed trajectory.
+ *
+ * pic_record: start a recorded run at the current state (any earlier
+ * recording is dropped).  The stored particle order at this call, as
+ * pic_get_particles returns it now, is the order of the gradient arrays of
+ * pic_backward.  checkpoint_every >= 1 (PIC_EINVAL otherwise); PIC_EINVAL
+ * for PIC_FP32_MIXED contexts; PIC_ESTATE before any load.  Every pic_step
+ * that follows is recorded; pic_load_particles and pic_set_fields end the
+ * recording.
+ *
+ * pic_backward: with seeds dL/d(state now), return dL/d(state at
+ * pic_record).  seed_fields[6] (Ex, Ey, Ez, Bx, By, Bz, n_cells values each)
+ * and grad_fields[6]: host or device arrays; NULL array or NULL entries mean
+ * zero seed / not wanted.  seed_particles and grad_particles: NULL or
+ * 6 * n_species pointers, entry [6 s + k] for species s and k = x, y, z, ux,
+ * uy, uz, each n_s values, in the current stored order (seeds) and in the
+ * stored order at pic_record (gradients); NULL entries as above.  Position
+ * gradients are per cell unit (positions are in cell units).  Afterwards the
+ * context holds the same state as before the call (particles, fields, J of
+ * the last step, counters) and the recording has ended.  PIC_ESTATE without
+ * a recording. */
+int pic_record(pic_ctx* ctx, int32_t checkpoint_every);
+int pic_backward(pic_ctx* ctx, const double* const seed_fields[6],
+                 const double* const* seed_particles, double* const grad_fields[6],
+                 double* const* grad_particles);
+
 /* Message of the last failure on ctx (or of the last failed pic_create when
  * ctx is NULL).  Owned by the library; valid until the next call. */
 const char* pic_last_error(const pic_ctx* ctx);

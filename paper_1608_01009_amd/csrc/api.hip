@@ -7,6 +7,8 @@
 // readout and is cleared by the Yee pass), the sort scratch and a device
 // error word.  All work is queued on the context's stream; pic_step waits
 // only for the final 4-byte error word.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,6 +53,20 @@ __global__ void iota_kernel(int64_t* id, int64_t n) {
          i += (int64_t)gridDim.x * blockDim.x)
         id[i] = i;
 }
+
+// A saved state of the context: per species the particles in stored order
+// (no pending re-sort) with ids and supercell offsets, E, B, the J of the
+// last step, and the step counters.  Device memory owned by the checkpoint.
+struct Checkpoint {
+    int64_t steps = 0;
+    int64_t rebins = 0;
+    int since_sort = 0;
+    std::vector<int64_t> n;
+    std::vector<Parts> parts;
+    std::vector<int*> sc_off;
+    double* EBJ[9] = {};
+    std::vector<void*> mem;
+};
 
 }  // namespace
 
@@ -99,6 +115,10 @@ struct pic_ctx {
     std::vector<TimedRange> ranges;
     std::vector<void*> allocs;
     std::string err;
+    bool recording = false;            // pic_record .. pic_backward
+    int rec_every = 1;
+    int64_t rec_start = 0;             // step count at pic_record
+    std::vector<Checkpoint> ckpts;     // at rec_start, rec_start + rec_every, ...
 };
 
 namespace {
@@ -127,8 +147,21 @@ hipError_t dalloc(pic_ctx* c, void** p, size_t bytes) {
     return e;
 }
 
+void free_checkpoint(Checkpoint& k) {
+    for (void* p : k.mem) (void)hipFree(p);
+    k.mem.clear();
+}
+
+void end_recording(pic_ctx* c) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& k : c->ckpts) free_checkpoint(k);
+    c->ckpts.clear();
+    c->recording = false;
+}
+
 void release(pic_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    end_recording(c);
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->h_err) (void)hipHostFree(c->h_err);
@@ -256,6 +289,268 @@ int resolve_pending(pic_ctx* c, SpeciesState& s) {
         HIPCHK(c, launch_permute_mixed(s.n, s.perm, s.bufm[s.cur], s.bufm[1 - s.cur], c->stream));
     s.cur = 1 - s.cur;
     s.pending = false;
+    return PIC_OK;
+}
+
+// One step of every species and the Yee update, queued on the stream
+// (no synchronisation); the re-sort order follows every R-th step.
+int step_once(pic_ctx* c) {
+    const Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
+    const Fields fo{{c->Eo[0], c->Eo[1], c->Eo[2]}, {c->Bo[0], c->Bo[1], c->Bo[2]}};
+    double* const* Jd = c->J[c->jdep];
+    const bool sort_after = (c->steps_since_sort + 1 == c->R);
+    for (auto& s : c->sp) {
+        if (s.n == 0) continue;
+        const bool mixed = c->precision == PIC_FP32_MIXED;
+        const Parts& src = s.buf[s.cur];
+        const Parts& dst = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
+        const PartsM& srcm = s.bufm[s.cur];
+        const PartsM& dstm = s.pending ? s.bufm[1 - s.cur] : s.bufm[s.cur];
+        const unsigned* perm = s.pending ? s.perm : nullptr;
+        unsigned* keys = sort_after ? s.keys : nullptr;
+        unsigned* fn = c->far_n + c->far_phase;
+        unsigned* fn_next = c->far_n + (1 - c->far_phase);
+        {
+            Timed t(c, s.pending ? ST_PUSH_PERM : ST_PUSH);
+            if (mixed)
+                HIPCHK(c, launch_push_mixed(c->g, s.cm, srcm, dstm, perm, keys, s.sc_off,
+                                            f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
+                                            fn_next, c->det, c->stream));
+            else
+                HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, perm, keys, s.sc_off,
+                                              f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
+                                              fn_next, c->det, c->stream));
+        }
+        {
+            Timed t(c, ST_FAR);
+            if (mixed)
+                HIPCHK(c, launch_far_mixed(c->g, s.cm, srcm, dstm, perm, keys, f, Jd,
+                                           c->d_err, c->d_nfar, c->far_q, fn, fn_next,
+                                           c->det, c->stream));
+            else
+                HIPCHK(c, launch_far_movers(c->g, s.c, src, dst, perm, keys, f, Jd,
+                                            c->d_err, c->d_nfar, c->far_q, fn, fn_next,
+                                            c->det, c->stream));
+        }
+        c->far_phase = 1 - c->far_phase;
+        if (c->timers) (s.pending ? c->push_perm_launches : c->push_launches)++;
+        if (s.pending) {
+            Timed t(c, ST_SORT);
+            HIPCHK(c, launch_permute_ids(s.n, s.perm, mixed ? srcm.id : src.id,
+                                         mixed ? dstm.id : dst.id, c->stream));
+            s.cur = 1 - s.cur;
+            s.pending = false;
+        }
+    }
+    {
+        Timed t(c, ST_FDTD);
+        if (c->det.hi[0]) HIPCHK(c, launch_j_from_fixed(c->g.ncell, c->det, Jd, c->stream));
+        HIPCHK(c, launch_fdtd(c->g, f, fo, Jd, c->J[c->jcur], c->stream));
+    }
+    for (int d = 0; d < 3; ++d) {
+        std::swap(c->E[d], c->Eo[d]);
+        std::swap(c->B[d], c->Bo[d]);
+    }
+    c->jcur = c->jdep;
+    c->jdep = 1 - c->jdep;
+    c->steps++;
+    if (c->timers) c->timed_steps++;
+    if (sort_after) {
+        Timed t(c, ST_SORT);
+        for (auto& s : c->sp) {
+            if (s.n == 0) continue;
+            int r = do_sort(c, s, s.keys);
+            if (r != PIC_OK) return r;
+        }
+        c->steps_since_sort = 0;
+        c->rebins++;
+    } else {
+        c->steps_since_sort++;
+    }
+    return PIC_OK;
+}
+
+hipError_t ck_alloc(std::vector<void*>& mem, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) mem.push_back(*p);
+    return e;
+}
+
+// Save the current state into k (allocating k's memory on first use).  A
+// pending re-sort is applied first, so the checkpoint holds the particles in
+// the order the next push reads them.
+int save_checkpoint(pic_ctx* c, Checkpoint& k) {
+    const size_t fb = (size_t)c->g.ncell * sizeof(double);
+    const size_t ob = (size_t)(c->g.nsc + 1) * sizeof(int);
+    const size_t ns = c->sp.size();
+    for (auto& s : c->sp) {
+        int r = resolve_pending(c, s);
+        if (r != PIC_OK) return r;
+    }
+    if (k.mem.empty()) {
+        k.n.assign(ns, 0);
+        k.parts.assign(ns, Parts{});
+        k.sc_off.assign(ns, nullptr);
+        for (int i = 0; i < 9; ++i) HIPCHK(c, ck_alloc(k.mem, (void**)&k.EBJ[i], fb));
+        for (size_t si = 0; si < ns; ++si) {
+            const size_t pb = (size_t)c->sp[si].n * sizeof(double);
+            Parts& P = k.parts[si];
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.x, pb));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.y, pb));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.z, pb));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.ux, pb));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.uy, pb));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.uz, pb));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&P.id, (size_t)c->sp[si].n * sizeof(int64_t)));
+            HIPCHK(c, ck_alloc(k.mem, (void**)&k.sc_off[si], ob));
+        }
+    }
+    const double* src[9] = {c->E[0], c->E[1], c->E[2], c->B[0], c->B[1], c->B[2],
+                            c->J[c->jcur][0], c->J[c->jcur][1], c->J[c->jcur][2]};
+    for (int i = 0; i < 9; ++i)
+        HIPCHK(c, hipMemcpyAsync(k.EBJ[i], src[i], fb, hipMemcpyDeviceToDevice, c->stream));
+    for (size_t si = 0; si < ns; ++si) {
+        const SpeciesState& s = c->sp[si];
+        const Parts& S = s.buf[s.cur];
+        const Parts& P = k.parts[si];
+        k.n[si] = s.n;
+        const size_t pb = (size_t)s.n * sizeof(double);
+        if (s.n > 0) {
+            HIPCHK(c, hipMemcpyAsync(P.x, S.x, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(P.y, S.y, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(P.z, S.z, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(P.ux, S.ux, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(P.uy, S.uy, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(P.uz, S.uz, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(P.id, S.id, (size_t)s.n * sizeof(int64_t),
+                                     hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(k.sc_off[si], s.sc_off, ob, hipMemcpyDeviceToDevice, c->stream));
+    }
+    k.steps = c->steps;
+    k.rebins = c->rebins;
+    k.since_sort = c->steps_since_sort;
+    return PIC_OK;
+}
+
+int restore_checkpoint(pic_ctx* c, const Checkpoint& k) {
+    const size_t fb = (size_t)c->g.ncell * sizeof(double);
+    const size_t ob = (size_t)(c->g.nsc + 1) * sizeof(int);
+    double* dst[9] = {c->E[0], c->E[1], c->E[2], c->B[0], c->B[1], c->B[2],
+                      c->J[c->jcur][0], c->J[c->jcur][1], c->J[c->jcur][2]};
+    for (int i = 0; i < 9; ++i)
+        HIPCHK(c, hipMemcpyAsync(dst[i], k.EBJ[i], fb, hipMemcpyDeviceToDevice, c->stream));
+    for (size_t si = 0; si < c->sp.size(); ++si) {
+        SpeciesState& s = c->sp[si];
+        s.pending = false;
+        s.n = k.n[si];
+        const Parts& D = s.buf[s.cur];
+        const Parts& P = k.parts[si];
+        const size_t pb = (size_t)s.n * sizeof(double);
+        if (s.n > 0) {
+            HIPCHK(c, hipMemcpyAsync(D.x, P.x, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(D.y, P.y, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(D.z, P.z, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(D.ux, P.ux, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(D.uy, P.uy, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(D.uz, P.uz, pb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(D.id, P.id, (size_t)s.n * sizeof(int64_t),
+                                     hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(s.sc_off, k.sc_off[si], ob, hipMemcpyDeviceToDevice, c->stream));
+    }
+    c->steps = k.steps;
+    c->rebins = k.rebins;
+    c->steps_since_sort = k.since_sort;
+    return PIC_OK;
+}
+
+// Reverse sweep over the recorded run (see pic_backward).  lEB and lam are
+// the adjoint of the current state on entry and of the recorded start on
+// return; the context's state is left at some recomputed step (the caller
+// restores it).
+int backward_sweep(pic_ctx* c, double* const lEB[6], std::vector<std::array<double*, 6>>& lam,
+                   std::vector<std::array<double*, 6>>& lam2, std::vector<void*>& mem) {
+    const size_t fb = (size_t)c->g.ncell * sizeof(double);
+    const size_t ns = c->sp.size();
+    const int64_t K = c->steps - c->rec_start;
+    const int every = c->rec_every;
+    const int seg_len = (int)std::min<int64_t>(every, K);
+    double* lJ[3];
+    for (int d = 0; d < 3; ++d) HIPCHK(c, ck_alloc(mem, (void**)&lJ[d], fb));
+    // forward state of every step of one segment
+    std::vector<std::array<double*, 6>> stEB(seg_len);
+    std::vector<std::vector<std::array<double*, 6>>> stP(seg_len,
+                                                         std::vector<std::array<double*, 6>>(ns));
+    std::vector<std::vector<unsigned*>> stPerm(seg_len, std::vector<unsigned*>(ns, nullptr));
+    std::vector<std::vector<char>> sorted(seg_len, std::vector<char>(ns, 0));
+    for (int j = 0; j < seg_len; ++j) {
+        for (int k = 0; k < 6; ++k) HIPCHK(c, ck_alloc(mem, (void**)&stEB[j][k], fb));
+        for (size_t si = 0; si < ns; ++si) {
+            const int64_t n = c->sp[si].n;
+            for (int k = 0; k < 6; ++k)
+                HIPCHK(c, ck_alloc(mem, (void**)&stP[j][si][k], (size_t)n * sizeof(double)));
+            HIPCHK(c, ck_alloc(mem, (void**)&stPerm[j][si], (size_t)n * sizeof(unsigned)));
+        }
+    }
+    for (int seg = (int)c->ckpts.size() - 1; seg >= 0; --seg) {
+        const int64_t s0 = c->ckpts[seg].steps - c->rec_start;
+        const int64_t s1 = std::min<int64_t>(s0 + every, K);
+        if (s1 <= s0) continue;
+        int r = restore_checkpoint(c, c->ckpts[seg]);
+        if (r != PIC_OK) return r;
+        const int len = (int)(s1 - s0);
+        for (int j = 0; j < len; ++j) {
+            const double* F[6] = {c->E[0], c->E[1], c->E[2], c->B[0], c->B[1], c->B[2]};
+            for (int k = 0; k < 6; ++k)
+                HIPCHK(c, hipMemcpyAsync(stEB[j][k], F[k], fb, hipMemcpyDeviceToDevice, c->stream));
+            for (size_t si = 0; si < ns; ++si) {
+                const SpeciesState& s = c->sp[si];
+                if (s.n == 0) continue;
+                const Parts& P = s.buf[s.cur];
+                const double* src[6] = {P.x, P.y, P.z, P.ux, P.uy, P.uz};
+                for (int k = 0; k < 6; ++k)
+                    HIPCHK(c, hipMemcpyAsync(stP[j][si][k], src[k], (size_t)s.n * sizeof(double),
+                                             hipMemcpyDeviceToDevice, c->stream));
+            }
+            r = step_once(c);
+            if (r != PIC_OK) return r;
+            for (size_t si = 0; si < ns; ++si) {
+                SpeciesState& s = c->sp[si];
+                sorted[j][si] = s.pending ? 1 : 0;
+                if (!s.pending) continue;
+                HIPCHK(c, hipMemcpyAsync(stPerm[j][si], s.perm, (size_t)s.n * sizeof(unsigned),
+                                         hipMemcpyDeviceToDevice, c->stream));
+                r = resolve_pending(c, s);
+                if (r != PIC_OK) return r;
+            }
+        }
+        for (int j = len - 1; j >= 0; --j) {
+            for (size_t si = 0; si < ns; ++si) {
+                const int64_t n = c->sp[si].n;
+                if (n == 0 || !sorted[j][si]) continue;
+                HIPCHK(c, launch_unpermute(n, stPerm[j][si], lam[si].data(), lam2[si].data(),
+                                           c->stream));
+                std::swap(lam[si], lam2[si]);
+            }
+            double* lE[3] = {lEB[0], lEB[1], lEB[2]};
+            double* lB[3] = {lEB[3], lEB[4], lEB[5]};
+            HIPCHK(c, launch_fdtd_adjoint(c->g, lE, lB, lJ, c->stream));
+            for (size_t si = 0; si < ns; ++si) {
+                const SpeciesState& s = c->sp[si];
+                if (s.n == 0) continue;
+                const double* st[6] = {stP[j][si][0], stP[j][si][1], stP[j][si][2],
+                                       stP[j][si][3], stP[j][si][4], stP[j][si][5]};
+                const double* F[6] = {stEB[j][0], stEB[j][1], stEB[j][2],
+                                      stEB[j][3], stEB[j][4], stEB[j][5]};
+                const double* lJc[3] = {lJ[0], lJ[1], lJ[2]};
+                HIPCHK(c, launch_particle_adjoint(c->g, s.c, s.n, st, F, lJc, lam[si].data(), lEB,
+                                                  c->stream));
+            }
+        }
+    }
     return PIC_OK;
 }
 
@@ -494,6 +789,7 @@ int pic_load_particles(pic_ctx* c, int32_t species, int64_t n, const double* x, 
     if (species < 0 || species >= (int)c->sp.size()) return fail(c, PIC_EINVAL, "bad species index");
     SpeciesState& s = c->sp[species];
     if (n < 0) return fail(c, PIC_EINVAL, "n must be >= 0");
+    if (c->recording) end_recording(c);
     if (n > s.capacity) return fail(c, PIC_ECAPACITY, "n exceeds the species capacity");
     if (bad_ptr(x, n) || bad_ptr(y, n) || bad_ptr(z, n) || bad_ptr(ux, n) || bad_ptr(uy, n) ||
         bad_ptr(uz, n))
@@ -555,6 +851,7 @@ int pic_set_fields(pic_ctx* c, const double* const EB[6]) {
     for (int k = 0; k < 6; ++k)
         if (!EB[k]) return fail(c, PIC_EINVAL, "EB entries must not be NULL");
     HIPCHK(c, hipSetDevice(c->device));
+    if (c->recording) end_recording(c);
     const size_t fb = (size_t)c->g.ncell * sizeof(double);
     for (int d = 0; d < 3; ++d) {
         HIPCHK(c, hipMemcpyAsync(c->E[d], EB[d], fb, hipMemcpyDefault, c->stream));
@@ -581,77 +878,12 @@ int pic_step(pic_ctx* c, int32_t n_steps) {
     {
         Timed total(c, ST_TOTAL);
         for (int it = 0; it < n_steps; ++it) {
-            const Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
-            const Fields fo{{c->Eo[0], c->Eo[1], c->Eo[2]}, {c->Bo[0], c->Bo[1], c->Bo[2]}};
-            double* const* Jd = c->J[c->jdep];
-            const bool sort_after = (c->steps_since_sort + 1 == c->R);
-            for (auto& s : c->sp) {
-                if (s.n == 0) continue;
-                const bool mixed = c->precision == PIC_FP32_MIXED;
-                const Parts& src = s.buf[s.cur];
-                const Parts& dst = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
-                const PartsM& srcm = s.bufm[s.cur];
-                const PartsM& dstm = s.pending ? s.bufm[1 - s.cur] : s.bufm[s.cur];
-                const unsigned* perm = s.pending ? s.perm : nullptr;
-                unsigned* keys = sort_after ? s.keys : nullptr;
-                unsigned* fn = c->far_n + c->far_phase;
-                unsigned* fn_next = c->far_n + (1 - c->far_phase);
-                {
-                    Timed t(c, s.pending ? ST_PUSH_PERM : ST_PUSH);
-                    if (mixed)
-                        HIPCHK(c, launch_push_mixed(c->g, s.cm, srcm, dstm, perm, keys, s.sc_off,
-                                                    f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
-                                                    fn_next, c->det, c->stream));
-                    else
-                        HIPCHK(c, launch_push_deposit(c->g, s.c, src, dst, perm, keys, s.sc_off,
-                                                      f, Jd, c->d_err, c->d_nfar, c->far_q, fn,
-                                                      fn_next, c->det, c->stream));
-                }
-                {
-                    Timed t(c, ST_FAR);
-                    if (mixed)
-                        HIPCHK(c, launch_far_mixed(c->g, s.cm, srcm, dstm, perm, keys, f, Jd,
-                                                   c->d_err, c->d_nfar, c->far_q, fn, fn_next,
-                                                   c->det, c->stream));
-                    else
-                        HIPCHK(c, launch_far_movers(c->g, s.c, src, dst, perm, keys, f, Jd,
-                                                    c->d_err, c->d_nfar, c->far_q, fn, fn_next,
-                                                    c->det, c->stream));
-                }
-                c->far_phase = 1 - c->far_phase;
-                if (c->timers) (s.pending ? c->push_perm_launches : c->push_launches)++;
-                if (s.pending) {
-                    Timed t(c, ST_SORT);
-                    HIPCHK(c, launch_permute_ids(s.n, s.perm, mixed ? srcm.id : src.id,
-                                                 mixed ? dstm.id : dst.id, c->stream));
-                    s.cur = 1 - s.cur;
-                    s.pending = false;
-                }
-            }
-            {
-                Timed t(c, ST_FDTD);
-                if (c->det.hi[0]) HIPCHK(c, launch_j_from_fixed(c->g.ncell, c->det, Jd, c->stream));
-                HIPCHK(c, launch_fdtd(c->g, f, fo, Jd, c->J[c->jcur], c->stream));
-            }
-            for (int d = 0; d < 3; ++d) {
-                std::swap(c->E[d], c->Eo[d]);
-                std::swap(c->B[d], c->Bo[d]);
-            }
-            c->jcur = c->jdep;
-            c->jdep = 1 - c->jdep;
-            c->steps++;
-            if (c->timers) c->timed_steps++;
-            if (sort_after) {
-                Timed t(c, ST_SORT);
-                for (auto& s : c->sp) {
-                    if (s.n == 0) continue;
-                    int r = do_sort(c, s, s.keys);
-                    if (r != PIC_OK) return r;
-                }
-                c->steps_since_sort = 0;
-                c->rebins++;
-            } else {
-                c->steps_since_sort++;
+            int r = step_once(c);
+            if (r != PIC_OK) return r;
+            if (c->recording && (c->steps - c->rec_start) % c->rec_every == 0) {
+                c->ckpts.emplace_back();
+                r = save_checkpoint(c, c->ckpts.back());
+                if (r != PIC_OK) return r;
             }
         }
     }
@@ -809,6 +1041,103 @@ int pic_get_counters(pic_ctx* c, int64_t out[4]) {
     out[3] = c->precision == PIC_FP64 ? push_deposit_lds_bytes(c->g, det)
                                       : push_mixed_lds_bytes(c->g, det);
     return PIC_OK;
+}
+
+int pic_record(pic_ctx* c, int32_t checkpoint_every) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (checkpoint_every < 1) return fail(c, PIC_EINVAL, "checkpoint_every must be >= 1");
+    if (c->precision != PIC_FP64)
+        return fail(c, PIC_EINVAL, "the adjoint supports PIC_FP64 contexts only");
+    if (!c->any_loaded) return fail(c, PIC_ESTATE, "pic_record before any pic_load_particles");
+    HIPCHK(c, hipSetDevice(c->device));
+    end_recording(c);
+    c->rec_every = checkpoint_every;
+    c->rec_start = c->steps;
+    c->recording = true;
+    c->ckpts.emplace_back();
+    int r = save_checkpoint(c, c->ckpts.back());
+    if (r == PIC_OK) r = sync_and_check(c, false);
+    if (r != PIC_OK) end_recording(c);
+    return r;
+}
+
+int pic_backward(pic_ctx* c, const double* const seed_fields[6],
+                 const double* const* seed_particles, double* const grad_fields[6],
+                 double* const* grad_particles) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!c->recording) return fail(c, PIC_ESTATE, "pic_backward without pic_record");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(unsigned), c->stream));
+    const size_t ns = c->sp.size();
+    const int64_t nc = c->g.ncell;
+    const size_t fb = (size_t)nc * sizeof(double);
+    std::vector<void*> mem;
+    Checkpoint fin;
+    unsigned long long nfar = 0;
+    const int timers = c->timers;
+    int r = PIC_OK;
+    auto run = [&]() -> int {
+        HIPCHK(c, hipMemcpyAsync(&nfar, c->d_nfar, sizeof(nfar), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int rr = save_checkpoint(c, fin);     // the current state; seeds are in its order
+        if (rr != PIC_OK) return rr;
+        double* lEB[6];
+        for (int k = 0; k < 6; ++k) {
+            HIPCHK(c, ck_alloc(mem, (void**)&lEB[k], fb));
+            if (seed_fields && seed_fields[k])
+                HIPCHK(c, hipMemcpyAsync(lEB[k], seed_fields[k], fb, hipMemcpyDefault, c->stream));
+            else
+                HIPCHK(c, launch_zero(lEB[k], nc, c->stream));
+        }
+        std::vector<std::array<double*, 6>> lam(ns), lam2(ns);
+        for (size_t si = 0; si < ns; ++si) {
+            const int64_t n = c->sp[si].n;
+            for (int k = 0; k < 6; ++k) {
+                HIPCHK(c, ck_alloc(mem, (void**)&lam[si][k], (size_t)n * sizeof(double)));
+                HIPCHK(c, ck_alloc(mem, (void**)&lam2[si][k], (size_t)n * sizeof(double)));
+                const double* sd = seed_particles ? seed_particles[6 * si + k] : nullptr;
+                if (sd && n > 0)
+                    HIPCHK(c, hipMemcpyAsync(lam[si][k], sd, (size_t)n * sizeof(double),
+                                             hipMemcpyDefault, c->stream));
+                else
+                    HIPCHK(c, launch_zero(lam[si][k], n, c->stream));
+            }
+        }
+        c->timers = 0;
+        rr = backward_sweep(c, lEB, lam, lam2, mem);
+        if (rr != PIC_OK) return rr;
+        for (int k = 0; k < 6; ++k)
+            if (grad_fields && grad_fields[k])
+                HIPCHK(c, hipMemcpyAsync(grad_fields[k], lEB[k], fb, hipMemcpyDefault, c->stream));
+        for (size_t si = 0; si < ns && grad_particles; ++si) {
+            const int64_t n = c->sp[si].n;
+            for (int k = 0; k < 6; ++k) {
+                double* gd = grad_particles[6 * si + k];
+                if (gd && n > 0)
+                    HIPCHK(c, hipMemcpyAsync(gd, lam[si][k], (size_t)n * sizeof(double),
+                                             hipMemcpyDefault, c->stream));
+            }
+        }
+        return PIC_OK;
+    };
+    r = run();
+    // back to the state of the call, whatever happened
+    c->timers = timers;
+    if (!fin.mem.empty()) {
+        int r2 = restore_checkpoint(c, fin);
+        if (r == PIC_OK) r = r2;
+        if (hipMemcpyAsync(c->d_nfar, &nfar, sizeof(nfar), hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess && r == PIC_OK)
+            r = fail(c, PIC_EDEVICE, "restoring the far-mover counter");
+    }
+    int r3 = sync_and_check(c, true);
+    if (r == PIC_OK) r = r3;
+    free_checkpoint(fin);
+    for (void* p : mem) (void)hipFree(p);
+    end_recording(c);
+    return r;
 }
 
 const char* pic_last_error(const pic_ctx* c) {

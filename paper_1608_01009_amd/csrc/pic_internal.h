@@ -178,6 +178,23 @@ hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, con
 hipError_t launch_permute_ids(int64_t n, const unsigned* perm, const int64_t* src, int64_t* dst,
                               hipStream_t s);
 
+// Adjoint of one step (FP64).  launch_fdtd_adjoint: the transposed Yee update
+// in place on (lE, lB), writing lJ (the adjoint of the step's current).
+// launch_particle_adjoint: one species' particle loop reversed from its state
+// at the start of the step (state = x, y, z, ux, uy, uz) and the fields at the
+// start of the step; lam (six arrays) holds the adjoint of the state after the
+// step on entry and before it on return; lEB accumulates the transposed
+// interpolation with atomics.  launch_unpermute: dst[perm[i]] = src[i] for six
+// arrays (the adjoint of a re-sort).
+hipError_t launch_fdtd_adjoint(const Geom& g, double* const lE[3], double* const lB[3],
+                               double* const lJ[3], hipStream_t s);
+hipError_t launch_particle_adjoint(const Geom& g, const SpeciesC& sp, int64_t n,
+                                   const double* const state[6], const double* const EB[6],
+                                   const double* const lJ[3], double* const lam[6],
+                                   double* const lEB[6], hipStream_t s);
+hipError_t launch_unpermute(int64_t n, const unsigned* perm, double* const src[6],
+                            double* const dst[6], hipStream_t s);
+
 // Diagnostics.
 hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, hipStream_t s);
 hipError_t launch_kinetic(const double* ux, const double* uy, const double* uz, int64_t n,

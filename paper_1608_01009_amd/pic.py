@@ -36,7 +36,8 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
 # the entry points declared in include/pic.h
 ABI_SYMBOLS = ("pic_create", "pic_load_particles", "pic_set_fields", "pic_step",
                "pic_get_fields", "pic_get_particles", "pic_diagnostics", "pic_enable_timers",
-               "pic_get_timers", "pic_get_counters", "pic_last_error", "pic_destroy")
+               "pic_get_timers", "pic_get_counters", "pic_record", "pic_backward",
+               "pic_last_error", "pic_destroy")
 
 
 class PicGrid(C.Structure):
@@ -89,6 +90,8 @@ def library():
         L.pic_enable_timers.argtypes = [V, C.c_int32]
         L.pic_get_timers.argtypes = [V, D]
         L.pic_get_counters.argtypes = [V, C.POINTER(C.c_int64)]
+        L.pic_record.argtypes = [V, C.c_int32]
+        L.pic_backward.argtypes = [V, C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V)]
         L.pic_last_error.argtypes = [V]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [V]
@@ -236,6 +239,42 @@ def pic_get_counters(ctx) -> np.ndarray:
     return out
 
 
+def pic_record(ctx, checkpoint_every: int):
+    _check(ctx, library().pic_record(ctx, int(checkpoint_every)))
+
+
+def pic_backward(ctx, ncell: int, counts: Sequence[int], seed_fields=None, seed_particles=None,
+                 grad_fields=None, grad_particles=None):
+    """Reverse sweep over the recorded run.  ``seed_fields``: six arrays or
+    None; ``seed_particles``: per species None or six arrays (x, y, z, ux, uy,
+    uz); ``grad_fields`` / ``grad_particles`` the same shapes as outputs
+    (allocated as NumPy arrays when None).  ``counts``: particles per species.
+    Returns (grad_fields, grad_particles)."""
+    ns = len(counts)
+    if grad_fields is None:
+        grad_fields = [np.empty(ncell) for _ in range(6)]
+    if grad_particles is None:
+        grad_particles = [[np.empty(int(n)) for _ in range(6)] for n in counts]
+    sf = None
+    if seed_fields is not None:
+        sf = (C.c_void_p * 6)(*[_addr(a, ncell, np.float64) for a in seed_fields])
+    sp = None
+    if seed_particles is not None:
+        flat = []
+        for s in range(ns):
+            arrs = seed_particles[s] if seed_particles[s] is not None else [None] * 6
+            flat += [_addr(a, int(counts[s]), np.float64) for a in arrs]
+        sp = (C.c_void_p * (6 * ns))(*flat)
+    gf = (C.c_void_p * 6)(*[_addr(a, ncell, np.float64) for a in grad_fields])
+    flat = []
+    for s in range(ns):
+        arrs = grad_particles[s] if grad_particles[s] is not None else [None] * 6
+        flat += [_addr(a, int(counts[s]), np.float64) for a in arrs]
+    gp = (C.c_void_p * (6 * ns))(*flat)
+    _check(ctx, library().pic_backward(ctx, sf, sp, gf, gp))
+    return grad_fields, grad_particles
+
+
 def pic_last_error(ctx=None) -> str:
     m = library().pic_last_error(ctx)
     return m.decode() if m else ""
@@ -288,6 +327,26 @@ class Simulation:
 
     def counters(self):
         return pic_get_counters(self.ctx)
+
+    def counts(self):
+        """Particles per species."""
+        return [self._count(s) for s in range(len(self.species))]
+
+    def _count(self, s):
+        L = library()
+        n = C.c_int64(0)
+        code = L.pic_get_particles(self.ctx, int(s), 0, C.byref(n), *([None] * 7))
+        if code not in (PIC_OK, PIC_ECAPACITY):
+            _check(self.ctx, code)
+        return int(n.value)
+
+    def record(self, checkpoint_every=20):
+        pic_record(self.ctx, checkpoint_every)
+
+    def backward(self, seed_fields=None, seed_particles=None, grad_fields=None,
+                 grad_particles=None):
+        return pic_backward(self.ctx, self.ncell, self.counts(), seed_fields, seed_particles,
+                            grad_fields, grad_particles)
 
     def close(self):
         if self.ctx is not None:
