@@ -32,7 +32,7 @@ _I64 = C.POINTER(C.c_int64)
 
 class OrcGrid(C.Structure):
     _fields_ = [("n", C.c_int64 * 3), ("dx", C.c_double * 3), ("dt", C.c_double),
-                ("S", C.c_int64)]
+                ("S", C.c_int64), ("absorb_x", C.c_int64)]
 
 
 def lib():
@@ -55,6 +55,11 @@ def lib():
         L.orc_sort_key.argtypes = [G, _D]
         L.orc_sort_key.restype = C.c_int64
         L.orc_rebin.argtypes = [G, C.c_int64, _D, _D, _D, _D, _D, _D, _I64]
+        L.orc_rebin.restype = C.c_int64
+        L.orc_laser_field.argtypes = [C.c_double] * 4
+        L.orc_laser_field.restype = C.c_double
+        L.orc_add_laser.argtypes = [G, _D, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                    C.c_double]
         L.orc_push_deposit.argtypes = [G, C.c_double, C.c_double, C.c_double, C.c_int64,
                                        _D, _D, _D, _D, _D, _D, PP6, PP3]
         L.orc_mixed_round_pos.argtypes = [C.c_double, C.c_int64]
@@ -91,13 +96,14 @@ def _ptrs(arrs):
     return (_D * len(arrs))(*[_dp(a) for a in arrs])
 
 
-def make_grid(n, dx=(1.0, 1.0, 1.0), dt=None, S=1) -> OrcGrid:
+def make_grid(n, dx=(1.0, 1.0, 1.0), dt=None, S=1, absorb_x=False) -> OrcGrid:
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(n[d])
         g.dx[d] = float(dx[d])
     g.dt = float(dt)
     g.S = int(S)
+    g.absorb_x = int(bool(absorb_x))
     return g
 
 
@@ -185,6 +191,16 @@ def adjoint_particles(g: OrcGrid, q, m, w, state, EB, lJ, lam, lEB):
                                 _ptrs(EB), _ptrs(lJ), *[_dp(a) for a in lam], _ptrs(lEB))
 
 
+def laser_field(E0, omega, T, t):
+    return lib().orc_laser_field(float(E0), float(omega), float(T), float(t))
+
+
+def add_laser(g: OrcGrid, Jy, plane, E0, omega, T, t):
+    """Jy += -2 E_L(t) / dx on the node plane x = plane (in place)."""
+    lib().orc_add_laser(C.byref(g), _dp(Jy), int(plane), float(E0), float(omega), float(T),
+                        float(t))
+
+
 def mixed_round_pos(x, n):
     """Positions as the mixed-precision variant stores them (integer cell +
     FP32 offset), as FP64 values."""
@@ -217,15 +233,22 @@ class OracleSim:
     cell units.  Field arrays are flat, x-fastest, ``n[0]*n[1]*n[2]`` long.
     """
 
-    def __init__(self, n, dx, dt, species, S=4, R=20, precision="fp64"):
+    def __init__(self, n, dx, dt, species, S=4, R=20, precision="fp64", absorb_x=False,
+                 laser=None):
+        """``absorb_x``: absorbing x boundaries with particle removal (FP64
+        only).  ``laser``: None or (E0, omega, T, plane), the soft current
+        sheet of ``orc_add_laser`` added every step at t = (step + 1/2) dt."""
         assert precision in ("fp64", "mixed")
+        assert not (absorb_x and precision != "fp64")
+        self.absorb_x = bool(absorb_x)
+        self.laser = None if laser is None else tuple(float(v) for v in laser[:3]) + (int(laser[3]),)
         self.precision = precision
         self.n = tuple(int(v) for v in n)
         self.dx = tuple(float(v) for v in dx)
         self.dt = float(dt)
         self.S = int(S)
         self.R = int(R)
-        self.g = make_grid(self.n, self.dx, self.dt, self.S)
+        self.g = make_grid(self.n, self.dx, self.dt, self.S, self.absorb_x)
         self.species = [tuple(float(v) for v in s) for s in species]
         nc = self.n[0] * self.n[1] * self.n[2]
         self.F = [np.zeros(nc) for _ in range(9)]
@@ -271,8 +294,10 @@ class OracleSim:
 
     def _sort(self, s):
         x, y, z, ux, uy, uz, ids = self.P[s]
-        lib().orc_rebin(C.byref(self.g), len(x), _dp(x), _dp(y), _dp(z), _dp(ux),
-                        _dp(uy), _dp(uz), _ip(ids))
+        kept = lib().orc_rebin(C.byref(self.g), len(x), _dp(x), _dp(y), _dp(z), _dp(ux),
+                               _dp(uy), _dp(uz), _ip(ids))
+        if kept < len(x):              # removed particles (absorbing x) dropped
+            self.P[s] = [np.ascontiguousarray(a[:kept]) for a in self.P[s]]
 
     def set_fields(self, EB):
         for c in range(6):
@@ -305,6 +330,10 @@ class OracleSim:
                 else:
                     L.orc_push_deposit(C.byref(self.g), q, m, w, len(x), _dp(x), _dp(y), _dp(z),
                                        _dp(ux), _dp(uy), _dp(uz), EB, J)
+            if self.laser is not None:
+                E0, om, T, plane = self.laser
+                L.orc_add_laser(C.byref(self.g), _dp(self.F[7]), plane, E0, om, T,
+                                (self.step_count + 0.5) * self.dt)
             L.orc_fdtd(C.byref(self.g), _ptrs(self.F[0:3]), _ptrs(self.F[3:6]),
                        _ptrs(self.F[6:9]))
             self.step_count += 1
@@ -391,7 +420,8 @@ class OracleSim:
         for s, (q, m, w) in enumerate(self.species):
             if self.P[s] is None:
                 continue
-            ux, uy, uz = self.P[s][3:6]
+            live = self.P[s][0] >= 0.0           # removed particles carry x = -1
+            ux, uy, uz = [np.ascontiguousarray(a[live]) for a in self.P[s][3:6]]
             K += lib().orc_kinetic(m, w, len(ux), _dp(ux), _dp(uy), _dp(uz))
         return K
 
@@ -403,5 +433,5 @@ class OracleSim:
                 L.orc_field_energy(C.byref(self.g), B, 3))
 
     def total_charge(self):
-        return sum(q * w * (0 if self.P[s] is None else len(self.P[s][0]))
+        return sum(q * w * (0 if self.P[s] is None else int(np.sum(self.P[s][0] >= 0.0)))
                    for s, (q, m, w) in enumerate(self.species))

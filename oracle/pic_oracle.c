@@ -50,6 +50,12 @@ static int64_t lin(const orc_grid* g, int64_t i, int64_t j, int64_t k) {
  * ------------------------------------------------------------------------- */
 static double lerp(double a, double b, double f) { return fma(f, b - a, a); }
 
+/* lattice value; with absorbing x boundaries points outside 0 <= i < n0 are 0 */
+static double fetch(const orc_grid* g, const double* F, int64_t i, int64_t j, int64_t k) {
+    if (g->absorb_x && (i < 0 || i >= g->n[0])) return 0.0;
+    return F[lin(g, i, j, k)];
+}
+
 void orc_gather(const orc_grid* g, const double* const EB[6], const double xp[3],
                 double out[6]) {
     for (int c = 0; c < 6; ++c) {
@@ -65,8 +71,8 @@ void orc_gather(const orc_grid* g, const double* const EB[6], const double xp[3]
         for (int cc = 0; cc < 2; ++cc) {
             double fy[2];
             for (int b = 0; b < 2; ++b) {
-                double f0 = EB[c][lin(g, i[0], i[1] + b, i[2] + cc)];
-                double f1 = EB[c][lin(g, i[0] + 1, i[1] + b, i[2] + cc)];
+                double f0 = fetch(g, EB[c], i[0], i[1] + b, i[2] + cc);
+                double f1 = fetch(g, EB[c], i[0] + 1, i[1] + b, i[2] + cc);
                 fy[b] = lerp(f0, f1, f[0]);
             }
             fz[cc] = lerp(fy[0], fy[1], f[1]);
@@ -183,6 +189,7 @@ static void vb_segment(const orc_grid* g, double* const J[3], const int64_t cell
                 int64_t idx[3] = {cell[0], cell[1], cell[2]};
                 idx[p] += bp;
                 idx[r] += br;
+                if (g->absorb_x && (idx[0] < 0 || idx[0] >= g->n[0])) continue;
                 J[d][lin(g, idx[0], idx[1], idx[2])] += flux * W;
             }
         }
@@ -291,11 +298,114 @@ static void full_e(const orc_grid* g, double* const E[3], double* const B[3],
             }
 }
 
+/* Absorbing x boundaries: the same updates on the inside points, the slot
+ * n0-1 of Ex, By, Bz held at zero, Mur on Ey, Ez at i = 0 and i = n0-1. */
+static void half_b_abs(const orc_grid* g, double* const E[3], double* const B[3]) {
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const double dx = g->dx[0], dy = g->dx[1], dz = g->dx[2];
+    const double hdt = 0.5 * g->dt;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = lin(g, i, j, k);
+                double cx = (E[2][lin(g, i, j + 1, k)] - E[2][c]) / dy -
+                            (E[1][lin(g, i, j, k + 1)] - E[1][c]) / dz;
+                B[0][c] = B[0][c] - hdt * cx;
+                if (i == nx - 1) {
+                    B[1][c] = 0.0;
+                    B[2][c] = 0.0;
+                    continue;
+                }
+                double cy = (E[0][lin(g, i, j, k + 1)] - E[0][c]) / dz -
+                            (E[2][lin(g, i + 1, j, k)] - E[2][c]) / dx;
+                double cz = (E[1][lin(g, i + 1, j, k)] - E[1][c]) / dx -
+                            (E[0][lin(g, i, j + 1, k)] - E[0][c]) / dy;
+                B[1][c] = B[1][c] - hdt * cy;
+                B[2][c] = B[2][c] - hdt * cz;
+            }
+}
+
+static void full_e_abs(const orc_grid* g, double* const E[3], double* const B[3],
+                       const double* const J[3]) {
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const double dx = g->dx[0], dy = g->dx[1], dz = g->dx[2];
+    const double dt = g->dt;
+    const double kmur = (dt - dx) / (dt + dx);
+    /* old values that the Mur condition needs */
+    const size_t plane = (size_t)(ny * nz);
+    double* old = (double*)malloc(8 * plane * sizeof(double));
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j) {
+            const size_t q = (size_t)(j + ny * k);
+            for (int d = 1; d < 3; ++d) {
+                old[(4 * (d - 1) + 0) * plane + q] = E[d][lin(g, 0, j, k)];
+                old[(4 * (d - 1) + 1) * plane + q] = E[d][lin(g, 1, j, k)];
+                old[(4 * (d - 1) + 2) * plane + q] = E[d][lin(g, nx - 1, j, k)];
+                old[(4 * (d - 1) + 3) * plane + q] = E[d][lin(g, nx - 2, j, k)];
+            }
+        }
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = lin(g, i, j, k);
+                if (i < nx - 1) {
+                    double cx = (B[2][c] - B[2][lin(g, i, j - 1, k)]) / dy -
+                                (B[1][c] - B[1][lin(g, i, j, k - 1)]) / dz;
+                    E[0][c] = E[0][c] + dt * (cx - J[0][c]);
+                } else {
+                    E[0][c] = 0.0;
+                }
+                if (i == 0 || i == nx - 1) continue;       /* Mur below */
+                double cy = (B[0][c] - B[0][lin(g, i, j, k - 1)]) / dz -
+                            (B[2][c] - B[2][lin(g, i - 1, j, k)]) / dx;
+                double cz = (B[1][c] - B[1][lin(g, i - 1, j, k)]) / dx -
+                            (B[0][c] - B[0][lin(g, i, j - 1, k)]) / dy;
+                E[1][c] = E[1][c] + dt * (cy - J[1][c]);
+                E[2][c] = E[2][c] + dt * (cz - J[2][c]);
+            }
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j) {
+            const size_t q = (size_t)(j + ny * k);
+            for (int d = 1; d < 3; ++d) {
+                const double e0 = old[(4 * (d - 1) + 0) * plane + q];
+                const double e1 = old[(4 * (d - 1) + 1) * plane + q];
+                const double eN = old[(4 * (d - 1) + 2) * plane + q];
+                const double eN1 = old[(4 * (d - 1) + 3) * plane + q];
+                E[d][lin(g, 0, j, k)] = e1 + kmur * (E[d][lin(g, 1, j, k)] - e0);
+                E[d][lin(g, nx - 1, j, k)] = eN1 + kmur * (E[d][lin(g, nx - 2, j, k)] - eN);
+            }
+        }
+    free(old);
+}
+
 void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
               const double* const J[3]) {
+    if (g->absorb_x) {
+        half_b_abs(g, E, B);
+        full_e_abs(g, E, B, J);
+        half_b_abs(g, E, B);
+        return;
+    }
     half_b(g, E, B);
     full_e(g, E, B, J);
     half_b(g, E, B);
+}
+
+double orc_laser_field(double E0, double omega, double T, double t) {
+    const double pi = 3.14159265358979323846;
+    if (!(t >= 0.0 && t <= T)) return 0.0;
+    const double env = sin(pi * t / T);
+    return E0 * (env * env) * sin(omega * t);
+}
+
+void orc_add_laser(const orc_grid* g, double* Jy, int64_t plane, double E0, double omega,
+                   double T, double t) {
+    const double s = (-2.0 * orc_laser_field(E0, omega, T, t)) / g->dx[0];
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j) {
+            const int64_t c = lin(g, plane, j, k);
+            Jy[c] = Jy[c] + s;
+        }
 }
 
 /* ---------------------------------------------------------------------------
@@ -310,6 +420,7 @@ void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
  * ------------------------------------------------------------------------- */
 int64_t orc_sort_key(const orc_grid* g, const double x[3]) {
     const int64_t S = g->S;
+    if (g->absorb_x && x[0] < 0.0) return g->n[0] * g->n[1] * g->n[2];   /* removed */
     int64_t c[3];
     for (int d = 0; d < 3; ++d) c[d] = (int64_t)floor(x[d]);
     int64_t ns0 = g->n[0] / S, ns1 = g->n[1] / S;
@@ -323,12 +434,13 @@ static void permute_d(double* a, const int64_t* perm, int64_t n, double* tmp) {
     memcpy(a, tmp, (size_t)n * sizeof(double));
 }
 
-void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
-               double* ux, double* uy, double* uz, int64_t* id) {
-    if (n <= 0) return;
-    const int64_t nkeys = g->n[0] * g->n[1] * g->n[2];
+int64_t orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
+                  double* ux, double* uy, double* uz, int64_t* id) {
+    if (n <= 0) return 0;
+    const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+    const int64_t nkeys = ncell + (g->absorb_x ? 1 : 0);   /* key ncell: removed */
     const int64_t S3 = g->S * g->S * g->S;
-    const int64_t nsc = nkeys / S3;
+    const int64_t nsc = ncell / S3;
     int64_t* key = (int64_t*)malloc((size_t)n * sizeof(int64_t));
     int64_t* cnt = (int64_t*)calloc((size_t)nkeys, sizeof(int64_t));
     int64_t* start = (int64_t*)malloc(((size_t)nkeys + 1) * sizeof(int64_t));
@@ -359,6 +471,8 @@ void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
                 if (cnt[k] > r) perm[pos++] = sorted[start[k] + r];
             }
     }
+    const int64_t kept = pos;
+    for (int64_t r = start[ncell]; r < n; ++r) perm[pos++] = sorted[r];   /* removed, at the end */
     permute_d(x, perm, n, tmp);
     permute_d(y, perm, n, tmp);
     permute_d(z, perm, n, tmp);
@@ -368,6 +482,7 @@ void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
     for (int64_t i = 0; i < n; ++i) itmp[i] = id[perm[i]];
     memcpy(id, itmp, (size_t)n * sizeof(int64_t));
     free(key); free(cnt); free(start); free(fill); free(sorted); free(perm); free(tmp); free(itmp);
+    return kept;
 }
 
 /* One species' particle loop for one step, in array order (Section 2: field
@@ -381,11 +496,16 @@ void orc_push_deposit(const orc_grid* g, double q, double m, double w, int64_t n
         double u[3] = {ux[p], uy[p], uz[p]};
         double f[6];
         double x1[3];
+        if (g->absorb_x && x0[0] < 0.0) continue;       /* removed earlier */
         orc_gather(g, EB, x0, f);
         orc_boris(q, m, g->dt, f, u);
         orc_advance(g, u, x0, x1);
         orc_deposit_vb(g, J, x0, x1, qw);
         orc_wrap(g, x1);
+        /* absorbing x: a particle that ends outside 0 <= x < n0 - 1 is removed
+         * (its current on outside points was dropped; the part on the
+         * boundary planes meets the Mur-updated Ey, Ez, which ignore J) */
+        if (g->absorb_x && !(x1[0] >= 0.0 && x1[0] < (double)(g->n[0] - 1))) x1[0] = -1.0;
         x[p] = x1[0]; y[p] = x1[1]; z[p] = x1[2];
         ux[p] = u[0]; uy[p] = u[1]; uz[p] = u[2];
     }
@@ -402,6 +522,7 @@ void orc_rho(const orc_grid* g, double q, double w, int64_t n, const double* x,
         double xp[3] = {x[p], y[p], z[p]};
         int64_t i[3];
         double f[3];
+        if (g->absorb_x && xp[0] < 0.0) continue;        /* removed */
         for (int d = 0; d < 3; ++d) {
             double fl = floor(xp[d]);
             i[d] = (int64_t)fl;

@@ -34,7 +34,26 @@ typedef struct {
     double dx[3];    /* cell size per dimension (physical units) */
     double dt;       /* time step */
     int64_t S;       /* supercell edge in cells (sort key only) */
+    int64_t absorb_x; /* 0: periodic in x; 1: absorbing x boundaries (see below) */
 } orc_grid;
+
+/* Absorbing x boundaries (absorb_x = 1; y and z stay periodic).
+ *   Lattice: the nodes i = 0 .. n0-1 are inside; the half points i + 1/2 are
+ *   inside for i = 0 .. n0-2, and the array slot i = n0-1 of Ex, By, Bz (x =
+ *   n0 - 1/2) lies outside and is held at zero.  Lattice points with x index
+ *   outside [0, n0) read as zero in the interpolation and receive no current.
+ *   Fields: the Yee update of Ey, Ez on the planes i = 0 and i = n0-1 is
+ *   replaced by the first-order Mur condition for waves leaving through x,
+ *     E^{n+1}[0]    = E^n[1]    + k (E^{n+1}[1]    - E^n[0]),
+ *     E^{n+1}[n0-1] = E^n[n0-2] + k (E^{n+1}[n0-2] - E^n[n0-1]),
+ *   k = (dt - dx) / (dt + dx) (c = 1); Ex, By, Bz at slot n0-1 stay zero.
+ *   Particles live in 0 <= x < n0 - 1.  A move that ends outside deposits
+ *   as any move (its current on outside points is dropped; what falls on the
+ *   boundary planes x = 0 and x = n0 - 1 meets the Mur-updated Ey, Ez, which
+ *   ignore J, and the held-zero slot of Ex), so only its path inside acts;
+ *   the particle is removed: marked with x = -1 (its other state as if it
+ *   had stayed) and skipped by every later step; the next re-sort drops it.
+ *   Sort key of a removed particle: n0 n1 n2 (after every cell). */
 
 /* CIC interpolation of the six field components at one position. */
 void orc_gather(const orc_grid* g, const double* const EB[6],
@@ -59,14 +78,24 @@ void orc_wrap(const orc_grid* g, double x[3]);
 void orc_fdtd(const orc_grid* g, double* const E[3], double* const B[3],
               const double* const J[3]);
 
+/* Laser source (extension: the injected wave of the laser-plasma benchmark).
+ * Adds the soft current sheet Jy += -2 E_L(t) / dx on the node plane x =
+ * plane, E_L(t) = E0 sin^2(pi t / T) sin(omega t) for 0 <= t <= T, else 0:
+ * in vacuum it radiates Ey = E_L travelling away from the plane on both
+ * sides (half the surface current, with c = 1). */
+double orc_laser_field(double E0, double omega, double T, double t);
+void orc_add_laser(const orc_grid* g, double* Jy, int64_t plane, double E0, double omega,
+                   double T, double t);
+
 /* Sort key (supercell-major, then local cell) of one in-domain position. */
 int64_t orc_sort_key(const orc_grid* g, const double x[3]);
 
 /* Re-sort of n particles: stable sort by orc_sort_key, then inside every
  * supercell the cells' particles interleaved in rounds (round r: the r-th
  * particle of each cell with more than r, in cell order).  Permutes the six
- * state arrays and id in place. */
-void orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
+ * state arrays and id in place; removed particles (absorbing x) go to the
+ * end in their previous order.  Returns the number of particles kept. */
+int64_t orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
                double* ux, double* uy, double* uz, int64_t* id);
 
 /* Particle loop of one species for one step: gather, Boris, advance,
