@@ -25,7 +25,7 @@
  *   Ex (i+1/2,j,k)  Ey (i,j+1/2,k)  Ez (i,j,k+1/2)
  *   Bx (i,j+1/2,k+1/2)  By (i+1/2,j,k+1/2)  Bz (i+1/2,j+1/2,k)
  *   Jx, Jy, Jz at the positions of Ex, Ey, Ez.
- * All boundaries are periodic.
+ * y and z are periodic; x is periodic or absorbing (bc_x below).
  *
  * Conventions for every entry point:
  *   - returns a pic_status; nothing throws across the ABI;
@@ -82,6 +82,26 @@ enum {
  * of the FP64 rounding of the largest possible contribution).  Limit: at most
  * 16383 particles of a species per supercell (PIC_ECAPACITY from pic_step). */
 
+/* Boundaries along x (y and z are always periodic).  The paper's benchmark
+ * is periodic; PIC_BC_ABSORBING serves the laser-plasma slab (an extension):
+ *   fields: the lattice nodes i = 0 .. n0-1 are inside, the half points
+ *     i + 1/2 for i = 0 .. n0-2; the slot i = n0-1 of Ex, By, Bz lies outside
+ *     and is held at zero; lattice points outside the box read as zero in the
+ *     gather and receive no current; Ey and Ez on the planes i = 0 and
+ *     i = n0-1 follow the first-order Mur condition for waves leaving the box,
+ *       E^{n+1}[0] = E^n[1] + k (E^{n+1}[1] - E^n[0]),  k = (dt - dx) / (dt + dx),
+ *     and the mirror at i = n0-1 (their current is ignored);
+ *   particles: live in 0 <= x < n0 - 1; a particle whose move ends outside
+ *     deposits that move (only its path inside acts) and is removed: it keeps
+ *     its slot with x = -1 until the next re-sort drops it, and the particle
+ *     count of the species shrinks then.
+ * Requires PIC_FP64 without deterministic_j and supercell 2 or 4 with halo 1
+ * or 2, and n0 >= 3; the adjoint does not support it. */
+enum {
+    PIC_BC_PERIODIC = 0,
+    PIC_BC_ABSORBING = 1
+};
+
 typedef struct {
     int32_t n[3];           /* cells per dimension; each a multiple of `supercell` */
     int32_t supercell;      /* S: supercell edge in cells (Section 4.3); 1..6 with halo 1,
@@ -91,7 +111,8 @@ typedef struct {
     int32_t precision;      /* PIC_FP64 or PIC_FP32_MIXED */
     int32_t deterministic_j;  /* 1: bit-reproducible current accumulation (below); 0: FP64
                                  atomics (sums in arbitrary order) */
-    int32_t reserved[2];    /* must be zero */
+    int32_t bc_x;           /* PIC_BC_PERIODIC or PIC_BC_ABSORBING */
+    int32_t reserved;       /* must be zero */
     void* stream;           /* hipStream_t to run on, or NULL for a library-owned stream */
 } pic_grid_t;
 
@@ -112,8 +133,9 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                const pic_species_t* species, int32_t n_species, pic_ctx** out);
 
 /* Replace the particles of one species with n particles (n <= capacity).
- * x, y, z in [0, n_d) and finite u are required (PIC_EINVAL otherwise; with
- * PIC_FP32_MIXED also |u| within the FP32 range).
+ * x, y, z in [0, n_d) (x in [0, n_0 - 1) with PIC_BC_ABSORBING) and finite u
+ * are required (PIC_EINVAL otherwise; with PIC_FP32_MIXED also |u| within the
+ * FP32 range).
  * id may be NULL (ids 0..n-1).  The particles are re-sorted as described
  * above (their input order breaks ties) and the re-sort counter restarts. */
 int pic_load_particles(pic_ctx* ctx, int32_t species, int64_t n,
@@ -123,6 +145,20 @@ int pic_load_particles(pic_ctx* ctx, int32_t species, int64_t n,
 
 /* Replace E and B (EB[0..5] = Ex, Ey, Ez, Bx, By, Bz); J is cleared. */
 int pic_set_fields(pic_ctx* ctx, const double* const EB[6]);
+
+/* Laser source (PIC_BC_ABSORBING contexts; an extension for the laser-plasma
+ * slab): every step adds the soft current sheet Jy += -2 E_L(t) / dx_0 on the
+ * node plane x = plane (1 <= plane <= n0-2), t = (step + 1/2) dt with `step`
+ * the number of steps taken since pic_create, and
+ *   E_L(t) = amplitude sin^2(pi t / duration) sin(omega t)  for 0 <= t <= duration,
+ * zero otherwise.  In vacuum the sheet radiates a linearly polarised plane
+ * wave Ey = E_L travelling away from it on both sides (c = 1); the part
+ * towards x = 0 leaves through the absorbing boundary.  In the units here
+ * the normalised amplitude a0 gives amplitude = a0 omega.  amplitude = 0
+ * switches the source off.  PIC_EINVAL for periodic contexts, a plane out of
+ * range or non-finite parameters (duration > 0, omega >= 0). */
+int pic_set_laser(pic_ctx* ctx, double amplitude, double omega, double duration,
+                  int32_t plane);
 
 /* Advance n_steps >= 0 steps.  Asynchronous on the context stream except for
  * one final 4-byte read of the device error word.  PIC_ENONFINITE if a
@@ -142,7 +178,7 @@ int pic_get_particles(pic_ctx* ctx, int32_t species, int64_t capacity, int64_t* 
 
 /* Diagnostics of the current state (not part of the timed path):
  * out[0] W_E = 1/2 sum E^2 dV, out[1] W_B, out[2] K = sum w m (gamma - 1),
- * out[3] total charge sum q w, out[4] max |G - G_ref| with G = div E - rho
+ * out[3] total charge sum q w (of the particles inside), out[4] max |G - G_ref| with G = div E - rho
  * (CIC rho at the nodes), out[5] max |div B - div B_ref|, out[6] time,
  * out[7] step count.  The references are taken at the first step or
  * diagnostics call after the last load or set_fields. */

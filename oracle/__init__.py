@@ -275,7 +275,7 @@ class OracleSim:
         self._sort(s)
         self.steps_since_sort = 0
 
-    def set_state(self, particles, EB, steps_since_sort):
+    def set_state(self, particles, EB, steps_since_sort, step_count=None):
         """Install a full state exactly as given (no sort): per species the
         arrays (x, y, z, ux, uy, uz, id) in stored order, the six E/B arrays
         and the number of steps since the last sort.  Used to take one step
@@ -286,6 +286,8 @@ class OracleSim:
         for c in range(6):
             self.F[c] = np.array(EB[c], dtype=np.float64).ravel().copy()
         self.steps_since_sort = int(steps_since_sort)
+        if step_count is not None:
+            self.step_count = int(step_count)       # the laser's clock
 
     def to_mixed(self, arrs):
         """x, y, z, ux, uy, uz as the mixed-precision variant stores them."""

@@ -100,6 +100,7 @@ struct pic_ctx {
     double* G0 = nullptr;
     double* divB0 = nullptr;
     double* d_acc = nullptr;                 // W_E, W_B, then one kinetic sum per species
+    double* d_live = nullptr;                // live particles per species (absorbing x)
     unsigned long long* d_max = nullptr;     // 2 words
     bool ref_dirty = true;
     bool any_loaded = false;
@@ -115,6 +116,10 @@ struct pic_ctx {
     std::vector<TimedRange> ranges;
     std::vector<void*> allocs;
     std::string err;
+    double laser_amp = 0.0;            // laser sheet (absorbing x only)
+    double laser_omega = 0.0;
+    double laser_T = 0.0;
+    int laser_plane = -1;              // -1: off
     bool recording = false;            // pic_record .. pic_backward
     int rec_every = 1;
     int64_t rec_start = 0;             // step count at pic_record
@@ -277,6 +282,15 @@ int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys) {
     HIPCHK(c, launch_sort(c->g, s.n, keys, s.buf[s.cur], s.perm, s.sc_off, c->scratch, c->d_err,
                           c->stream));
     s.pending = true;
+    if (c->g.absorb_x && s.n > 0) {
+        // removed particles were sorted after every supercell: the species
+        // keeps the first sc_off[nsc]
+        int kept = 0;
+        HIPCHK(c, hipMemcpyAsync(&kept, s.sc_off + c->g.nsc, sizeof(int), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        s.n = kept;
+    }
     return PIC_OK;
 }
 
@@ -345,7 +359,24 @@ int step_once(pic_ctx* c) {
     {
         Timed t(c, ST_FDTD);
         if (c->det.hi[0]) HIPCHK(c, launch_j_from_fixed(c->g.ncell, c->det, Jd, c->stream));
-        HIPCHK(c, launch_fdtd(c->g, f, fo, Jd, c->J[c->jcur], c->stream));
+        if (c->g.absorb_x) {
+            // the laser sheet's current at t = (step + 1/2) dt
+            double lj = 0.0;
+            if (c->laser_plane >= 0) {
+                const double t = ((double)c->steps + 0.5) * c->g.dt;
+                double el = 0.0;
+                if (t >= 0.0 && t <= c->laser_T) {
+                    const double pi = 3.14159265358979323846;
+                    const double env = std::sin(pi * t / c->laser_T);
+                    el = c->laser_amp * (env * env) * std::sin(c->laser_omega * t);
+                }
+                lj = (-2.0 * el) / c->g.dx[0];
+            }
+            HIPCHK(c, launch_fdtd_absorbing(c->g, f, fo, Jd, c->J[c->jcur], c->laser_plane, lj,
+                                            c->stream));
+        } else {
+            HIPCHK(c, launch_fdtd(c->g, f, fo, Jd, c->J[c->jcur], c->stream));
+        }
     }
     for (int d = 0; d < 3; ++d) {
         std::swap(c->E[d], c->Eo[d]);
@@ -570,8 +601,9 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     if (!grid || !dx) return bad("grid and dx must not be NULL");
     if (n_species < 1 || n_species > 64 || !species)
         return bad("n_species must be in [1, 64] with a species array");
-    for (int r = 0; r < 2; ++r)
-        if (grid->reserved[r] != 0) return bad("reserved grid fields must be zero");
+    if (grid->reserved != 0) return bad("the reserved grid field must be zero");
+    if (grid->bc_x != PIC_BC_PERIODIC && grid->bc_x != PIC_BC_ABSORBING)
+        return bad("bc_x must be PIC_BC_PERIODIC or PIC_BC_ABSORBING");
     if (grid->deterministic_j != 0 && grid->deterministic_j != 1)
         return bad("deterministic_j must be 0 or 1");
     if (grid->precision != PIC_FP64 && grid->precision != PIC_FP32_MIXED)
@@ -585,6 +617,13 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     const int h = grid->halo == 0 ? 1 : grid->halo;
     if (!push_deposit_supported(S, h))
         return bad("unsupported (supercell, halo) pair: the LDS tiles would not fit");
+    if (grid->bc_x == PIC_BC_ABSORBING) {
+        if (grid->precision != PIC_FP64 || grid->deterministic_j)
+            return bad("PIC_BC_ABSORBING needs PIC_FP64 without deterministic_j");
+        if (!((S == 2 || S == 4) && (h == 1 || h == 2)))
+            return bad("PIC_BC_ABSORBING needs supercell 2 or 4 with halo 1 or 2");
+        if (grid->n[0] < 3) return bad("PIC_BC_ABSORBING needs n[0] >= 3");
+    }
     int64_t ncell = 1;
     for (int d = 0; d < 3; ++d) {
         if (grid->n[d] < 1) return bad("grid dimensions must be >= 1");
@@ -643,6 +682,7 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
     g.nsc = g.ns[0] * g.ns[1] * g.ns[2];
     g.h = h;
     g.dt = dt;
+    g.absorb_x = grid->bc_x == PIC_BC_ABSORBING ? 1 : 0;
     c->R = grid->rebin_every;
     c->precision = grid->precision;
 
@@ -661,6 +701,7 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         (e = dalloc(c, (void**)&c->G0, fb)) != hipSuccess ||
         (e = dalloc(c, (void**)&c->divB0, fb)) != hipSuccess ||
         (e = dalloc(c, (void**)&c->d_acc, (2 + 64) * sizeof(double))) != hipSuccess ||
+        (e = dalloc(c, (void**)&c->d_live, 64 * sizeof(double))) != hipSuccess ||
         (e = dalloc(c, (void**)&c->d_max, 2 * sizeof(unsigned long long))) != hipSuccess ||
         (e = dalloc(c, (void**)&c->d_err, 256)) != hipSuccess ||
         (e = dalloc(c, (void**)&c->d_nfar, 256)) != hipSuccess ||
@@ -864,6 +905,23 @@ int pic_set_fields(pic_ctx* c, const double* const EB[6]) {
     return PIC_OK;
 }
 
+int pic_set_laser(pic_ctx* c, double amplitude, double omega, double duration,
+                  int32_t plane) {
+    if (!c) return PIC_EINVAL;
+    c->err.clear();
+    if (!c->g.absorb_x) return fail(c, PIC_EINVAL, "the laser source needs PIC_BC_ABSORBING");
+    if (!std::isfinite(amplitude) || !std::isfinite(omega) || !(omega >= 0.0) ||
+        !std::isfinite(duration) || !(duration > 0.0))
+        return fail(c, PIC_EINVAL, "laser: finite amplitude, omega >= 0 and duration > 0 needed");
+    if (plane < 1 || plane > c->g.n[0] - 2)
+        return fail(c, PIC_EINVAL, "laser plane must lie in [1, n0 - 2]");
+    c->laser_amp = amplitude;
+    c->laser_omega = omega;
+    c->laser_T = duration;
+    c->laser_plane = amplitude == 0.0 ? -1 : plane;
+    return PIC_OK;
+}
+
 int pic_step(pic_ctx* c, int32_t n_steps) {
     if (!c) return PIC_EINVAL;
     c->err.clear();
@@ -952,13 +1010,26 @@ int pic_diagnostics(pic_ctx* c, double out[8]) {
     HIPCHK(c, launch_sum_squares(Bp, nc, c->d_acc + 1, c->stream));
     const double dv = c->g.dx[0] * c->g.dx[1] * c->g.dx[2];
     double qtot = 0.0;
+    std::vector<double> live(c->sp.size(), 0.0);
+    double* d_live = c->d_live;
+    if (c->g.absorb_x) HIPCHK(c, launch_zero(d_live, (int64_t)c->sp.size(), c->stream));
     for (size_t k = 0; k < c->sp.size(); ++k) {
         const SpeciesState& s = c->sp[k];
-        qtot += s.c.q * s.c.w * (double)s.n;
+        if (!c->g.absorb_x) qtot += s.c.q * s.c.w * (double)s.n;
         if (s.n == 0) continue;
         Parts P;
         HIPCHK(c, fp64_view(c, s, P));
-        HIPCHK(c, launch_kinetic(P.ux, P.uy, P.uz, s.n, c->d_acc + 2 + k, c->stream));
+        if (c->g.absorb_x)
+            HIPCHK(c, launch_kinetic(P.ux, P.uy, P.uz, s.n, c->d_acc + 2 + k, c->stream, P.x,
+                                     d_live + k));
+        else
+            HIPCHK(c, launch_kinetic(P.ux, P.uy, P.uz, s.n, c->d_acc + 2 + k, c->stream));
+    }
+    if (c->g.absorb_x) {
+        HIPCHK(c, hipMemcpyAsync(live.data(), d_live, live.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < c->sp.size(); ++k) qtot += c->sp[k].c.q * c->sp[k].c.w * live[k];
     }
     // rho, Gauss residual and div B against the references
     HIPCHK(c, launch_zero(c->rho, nc, c->stream));
@@ -1049,6 +1120,8 @@ int pic_record(pic_ctx* c, int32_t checkpoint_every) {
     if (checkpoint_every < 1) return fail(c, PIC_EINVAL, "checkpoint_every must be >= 1");
     if (c->precision != PIC_FP64)
         return fail(c, PIC_EINVAL, "the adjoint supports PIC_FP64 contexts only");
+    if (c->g.absorb_x)
+        return fail(c, PIC_EINVAL, "the adjoint supports periodic boundaries only");
     if (!c->any_loaded) return fail(c, PIC_ESTATE, "pic_record before any pic_load_particles");
     HIPCHK(c, hipSetDevice(c->device));
     end_recording(c);

@@ -46,14 +46,23 @@ __global__ void __launch_bounds__(kBlock) sumsq_kernel(const double* a, const do
 
 __global__ void __launch_bounds__(kBlock) kinetic_kernel(const double* ux, const double* uy,
                                                          const double* uz, int64_t n,
-                                                         double* acc) {
+                                                         double* acc, const double* x,
+                                                         double* cnt) {
     __shared__ double red[kBlock];
-    double s = 0.0;
+    double s = 0.0, live = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
+         i += (int64_t)gridDim.x * kBlock) {
+        if (x && x[i] < 0.0) continue;       // removed (absorbing x)
         s += sqrt(1.0 + ((ux[i] * ux[i] + uy[i] * uy[i]) + uz[i] * uz[i])) - 1.0;
+        live += 1.0;
+    }
     s = block_sum(s, red);
     if (threadIdx.x == 0) unsafeAtomicAdd(acc, s);
+    if (cnt) {
+        __syncthreads();
+        live = block_sum(live, red);
+        if (threadIdx.x == 0) unsafeAtomicAdd(cnt, live);
+    }
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -68,6 +77,7 @@ __global__ void __launch_bounds__(kBlock) rho_kernel(Geom g, double qv, const do
     for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * kBlock) {
         const double xp[3] = {x[p], y[p], z[p]};
+        if (xp[0] < 0.0) continue;             // removed (absorbing x)
         int i[3];
         double f[3];
         for (int d = 0; d < 3; ++d) {
@@ -98,6 +108,8 @@ __global__ void __launch_bounds__(kBlock) gauss_kernel(Geom g, const double* ex,
         const int km = (k == 0) ? c + (nz - 1) * nx * ny : c - nx * ny;
         out[c] = ((ex[c] - ex[im]) / g.dx[0] + (ey[c] - ey[jm]) / g.dx[1] +
                   (ez[c] - ez[km]) / g.dx[2]) - rho[c];
+        // absorbing x: the Mur planes do not follow Gauss's law
+        if (g.absorb_x && (i == 0 || i == nx - 1)) out[c] = 0.0;
     }
 }
 
@@ -111,6 +123,7 @@ __global__ void __launch_bounds__(kBlock) divb_kernel(Geom g, const double* bx, 
         const int kp = (k + 1 == nz) ? c - k * nx * ny : c + nx * ny;
         out[c] = (bx[ip] - bx[c]) / g.dx[0] + (by[jp] - by[c]) / g.dx[1] +
                  (bz[kp] - bz[c]) / g.dx[2];
+        if (g.absorb_x && i == nx - 1) out[c] = 0.0;   // the cell outside the box
     }
 }
 
@@ -141,9 +154,10 @@ hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, 
 }
 
 hipError_t launch_kinetic(const double* ux, const double* uy, const double* uz, int64_t n,
-                          double* acc, hipStream_t s) {
+                          double* acc, hipStream_t s, const double* x, double* cnt) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kinetic_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, ux, uy, uz, n, acc);
+    hipLaunchKernelGGL(kinetic_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, ux, uy, uz, n, acc,
+                       x, cnt);
     return hipGetLastError();
 }
 

@@ -199,6 +199,145 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
+namespace {
+
+// ---- absorbing x boundaries --------------------------------------------
+// Plain global-memory passes (see include/pic.h for the boundary scheme):
+// half B out of place, E with the Mur planes and the laser sheet, half B in
+// place.  x indices stay inside [0, n0); y and z wrap.
+
+struct AbsArgs {
+    int n[3];
+    double dt, hdt;
+    double dx[3];
+    int plane;          // laser sheet node plane, -1: none
+    double laser;       // Jy added on that plane this step
+};
+
+__device__ __forceinline__ int lin_abs(const AbsArgs& a, int i, int j, int k) {
+    j = j < 0 ? j + a.n[1] : (j >= a.n[1] ? j - a.n[1] : j);
+    k = k < 0 ? k + a.n[2] : (k >= a.n[2] ? k - a.n[2] : k);
+    return i + a.n[0] * (j + a.n[1] * k);
+}
+
+// Bo = B - dt/2 curl E; the slot n0-1 of By, Bz (outside) is zero.  Bo may
+// equal B (each thread reads and writes its own cell only).
+__global__ void __launch_bounds__(kBlock) abs_half_b_kernel(AbsArgs a, const double* Ex,
+                                                           const double* Ey, const double* Ez,
+                                                           const double* Bx, const double* By,
+                                                           const double* Bz, double* Box,
+                                                           double* Boy, double* Boz) {
+#pragma clang fp contract(off)
+    const int nx = a.n[0], ncell = a.n[0] * a.n[1] * a.n[2];
+    const double dx = a.dx[0], dy = a.dx[1], dz = a.dx[2];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        const int i = c % nx, j = (c / nx) % a.n[1], k = c / (nx * a.n[1]);
+        const double cx = (Ez[lin_abs(a, i, j + 1, k)] - Ez[c]) / dy -
+                          (Ey[lin_abs(a, i, j, k + 1)] - Ey[c]) / dz;
+        Box[c] = Bx[c] - a.hdt * cx;
+        if (i == nx - 1) {
+            Boy[c] = 0.0;
+            Boz[c] = 0.0;
+            continue;
+        }
+        const double cy = (Ex[lin_abs(a, i, j, k + 1)] - Ex[c]) / dz -
+                          (Ez[lin_abs(a, i + 1, j, k)] - Ez[c]) / dx;
+        const double cz = (Ey[lin_abs(a, i + 1, j, k)] - Ey[c]) / dx -
+                          (Ex[lin_abs(a, i, j + 1, k)] - Ex[c]) / dy;
+        Boy[c] = By[c] - a.hdt * cy;
+        Boz[c] = Bz[c] - a.hdt * cz;
+    }
+}
+
+struct Ey2 {
+    double y, z;
+};
+
+// E_y, E_z after the curl update at an inside plane 1 <= i <= n0-2 (the laser
+// sheet's current added to Jy on its plane)
+__device__ __forceinline__ Ey2 e_inside(const AbsArgs& a, int i, int j, int k,
+                                        const double* const E[3], const double* const B[3],
+                                        const double* const J[3]) {
+#pragma clang fp contract(off)
+    const int c = lin_abs(a, i, j, k);
+    const double dx = a.dx[0], dy = a.dx[1], dz = a.dx[2];
+    const double cy = (B[0][c] - B[0][lin_abs(a, i, j, k - 1)]) / dz -
+                      (B[2][c] - B[2][lin_abs(a, i - 1, j, k)]) / dx;
+    const double cz = (B[1][c] - B[1][lin_abs(a, i - 1, j, k)]) / dx -
+                      (B[0][c] - B[0][lin_abs(a, i, j - 1, k)]) / dy;
+    double jy = J[1][c];
+    if (i == a.plane) jy = jy + a.laser;
+    return {E[1][c] + a.dt * (cy - jy), E[2][c] + a.dt * (cz - J[2][c])};
+}
+
+__global__ void __launch_bounds__(kBlock) abs_e_kernel(AbsArgs a, const double* E0,
+                                                      const double* E1, const double* E2,
+                                                      const double* B0, const double* B1,
+                                                      const double* B2, double* J0, double* J1,
+                                                      double* J2, double* Eo0, double* Eo1,
+                                                      double* Eo2, double* Jc0, double* Jc1,
+                                                      double* Jc2) {
+#pragma clang fp contract(off)
+    const int nx = a.n[0], ncell = a.n[0] * a.n[1] * a.n[2];
+    const double dy = a.dx[1], dz = a.dx[2];
+    const double kmur = (a.dt - a.dx[0]) / (a.dt + a.dx[0]);
+    const double* const E[3] = {E0, E1, E2};
+    const double* const B[3] = {B0, B1, B2};
+    const double* const J[3] = {J0, J1, J2};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        const int i = c % nx, j = (c / nx) % a.n[1], k = c / (nx * a.n[1]);
+        if (i < nx - 1) {
+            const double cx = (B[2][c] - B[2][lin_abs(a, i, j - 1, k)]) / dy -
+                              (B[1][c] - B[1][lin_abs(a, i, j, k - 1)]) / dz;
+            Eo0[c] = E[0][c] + a.dt * (cx - J[0][c]);
+        } else {
+            Eo0[c] = 0.0;
+        }
+        if (i == 0 || i == nx - 1) {
+            // first-order Mur: the inside neighbour's new value, recomputed here
+            const int in = (i == 0) ? 1 : nx - 2;
+            const int cn = lin_abs(a, in, j, k);
+            const Ey2 en = e_inside(a, in, j, k, E, B, J);
+            Eo1[c] = E[1][cn] + kmur * (en.y - E[1][c]);
+            Eo2[c] = E[2][cn] + kmur * (en.z - E[2][c]);
+        } else {
+            const Ey2 e = e_inside(a, i, j, k, E, B, J);
+            Eo1[c] = e.y;
+            Eo2[c] = e.z;
+        }
+        if (i == a.plane) J1[c] = J[1][c] + a.laser;   // the source is part of this step's J
+        Jc0[c] = 0.0;
+        Jc1[c] = 0.0;
+        Jc2[c] = 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fdtd_absorbing(const Geom& g, const Fields& f, const Fields& fo,
+                                 double* const J[3], double* const Jclear[3], int laser_plane,
+                                 double laser_j, hipStream_t s) {
+    AbsArgs a;
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = g.n[d];
+        a.dx[d] = g.dx[d];
+    }
+    a.dt = g.dt;
+    a.hdt = 0.5 * g.dt;
+    a.plane = laser_plane;
+    a.laser = laser_j;
+    int nb = (g.ncell + kBlock - 1) / kBlock;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(abs_half_b_kernel, dim3(nb), dim3(kBlock), 0, s, a, f.E[0], f.E[1],
+                       f.E[2], f.B[0], f.B[1], f.B[2], fo.B[0], fo.B[1], fo.B[2]);
+    hipLaunchKernelGGL(abs_e_kernel, dim3(nb), dim3(kBlock), 0, s, a, f.E[0], f.E[1], f.E[2],
+                       fo.B[0], fo.B[1], fo.B[2], J[0], J[1], J[2], fo.E[0], fo.E[1], fo.E[2],
+                       Jclear[0], Jclear[1], Jclear[2]);
+    hipLaunchKernelGGL(abs_half_b_kernel, dim3(nb), dim3(kBlock), 0, s, a, fo.E[0], fo.E[1],
+                       fo.E[2], fo.B[0], fo.B[1], fo.B[2], fo.B[0], fo.B[1], fo.B[2]);
+    return hipGetLastError();
+}
+
 hipError_t launch_fdtd(const Geom& g, const Fields& f, const Fields& fo, double* const J[3],
                        double* const Jclear[3], hipStream_t s) {
     FArgs a;

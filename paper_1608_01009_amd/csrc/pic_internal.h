@@ -53,6 +53,7 @@ struct Geom {
     double dt;
     double cdt[3];     // dt / dx_d
     double dx[3];
+    int absorb_x;      // 1: absorbing x boundaries (Mur fields, particle removal)
 };
 
 // Per-species constants of the particle push.
@@ -162,6 +163,13 @@ hipError_t launch_j_from_fixed(int64_t n, const DetJ& det, double* const J[3], h
 hipError_t launch_fdtd(const Geom& g, const Fields& f, const Fields& fo, double* const J[3],
                        double* const Jclear[3], hipStream_t s);
 
+// The same update with absorbing x boundaries (Mur planes, outside slots
+// held at zero) and the laser sheet: laser_j is added to Jy on the node plane
+// laser_plane (-1: none) and kept in J.
+hipError_t launch_fdtd_absorbing(const Geom& g, const Fields& f, const Fields& fo,
+                                 double* const J[3], double* const Jclear[3], int laser_plane,
+                                 double laser_j, hipStream_t s);
+
 // Fill n doubles with zero.
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 
@@ -197,8 +205,11 @@ hipError_t launch_unpermute(int64_t n, const unsigned* perm, double* const src[6
 
 // Diagnostics.
 hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, hipStream_t s);
+// kinetic sum of gamma - 1; with x given, particles with x < 0 (removed) are
+// skipped and the others counted into cnt
 hipError_t launch_kinetic(const double* ux, const double* uy, const double* uz, int64_t n,
-                          double* acc, hipStream_t s);
+                          double* acc, hipStream_t s, const double* x = nullptr,
+                          double* cnt = nullptr);
 hipError_t launch_rho(const Geom& g, double qv, const double* x, const double* y,
                       const double* z, int64_t n, double* rho, hipStream_t s);
 hipError_t launch_gauss(const Geom& g, const Fields& f, const double* rho, double* out,

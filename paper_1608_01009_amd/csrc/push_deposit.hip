@@ -349,7 +349,10 @@ __device__ __forceinline__ constexpr int jt_off(int j) {
 // GATHER: particle i of this step is read from src at perm[i] (the step after
 // a re-sort), otherwise at i.
 // DET: the J tile and the flush use the exact integer split (DetJ).
-template <int S, int H, bool GATHER, bool DET>
+// ABS: absorbing x boundaries: lattice points outside 0 <= x < n0 read zero
+// and receive no current; a particle whose move ends outside 0 <= x < n0 - 1
+// is stored with x = -1 (removed) and later skipped.
+template <int S, int H, bool GATHER, bool DET, bool ABS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 push_deposit_kernel(const PDArgs a) {
     using EL = EBLayout<S, H>;
@@ -406,8 +409,9 @@ push_deposit_kernel(const PDArgs a) {
         const int tz = r / T2, ty = (r / T) % T, tx = r % T;
         const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
         const int li = tx + EL::PY * ty + EL::PZ * tz;
+        const bool outside = ABS && (org[0] + tx < 0 || org[0] + tx >= nx);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = a.EB[c][gi];
+        for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = outside ? 0.0 : a.EB[c][gi];
     }
     for (int t = threadIdx.x; t < JT_BYTES / 4; t += kBlock) ((int*)jraw)[t] = 0;
     __syncthreads();
@@ -498,7 +502,11 @@ push_deposit_kernel(const PDArgs a) {
         // prefetched loads does not also wait for this particle's stores.
         unsigned o = a.dst.spare;
         double xw[3] = {0.0, 0.0, 0.0};
-        if (valid) {
+        // removed particles (absorbing x) keep their slot untouched; a
+        // re-sort that follows sorts them after every cell
+        const bool dead = ABS && valid && x0[0] < 0.0;
+        if (dead && a.keys) a.keys[ip] = (unsigned)g.ncell;
+        if (valid && !dead) {
             // stored positions lie in [0, L) (this also rejects NaN); a
             // non-finite momentum shows up in the pushed state checked below
             bool ok = (x0[0] >= 0.0 && x0[0] < L[0]) && (x0[1] >= 0.0 && x0[1] < L[1]) &&
@@ -544,6 +552,7 @@ push_deposit_kernel(const PDArgs a) {
                 // positions are stored wrapped into [0, n)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) xw[d] = wrap_coord(x1[d], L[d]);
+                if (ABS && !(x1[0] >= 0.0 && x1[0] < L[0] - 1.0)) xw[0] = -1.0;   // removed
                 o = (unsigned)ip;
             }
         }
@@ -555,7 +564,8 @@ push_deposit_kernel(const PDArgs a) {
             *(double*)((char*)a.dst.ux + b) = u[0];
             *(double*)((char*)a.dst.uy + b) = u[1];
             *(double*)((char*)a.dst.uz + b) = u[2];
-            if (a.keys && o != a.dst.spare) a.keys[o] = sort_key<S>(g, xw);
+            if (a.keys && o != a.dst.spare)
+                a.keys[o] = (ABS && xw[0] < 0.0) ? (unsigned)g.ncell : sort_key<S>(g, xw);
         }
 
         // Far movers (outside the tile window) are left untouched here and
@@ -603,6 +613,7 @@ push_deposit_kernel(const PDArgs a) {
     for (int r = threadIdx.x; r < TJ3; r += kBlock) {
         const int tz = r / TJ2, ty = (r / TJ) % TJ, tx = r % TJ;
         const int li = tx + PY * ty + PZ * tz;
+        if (ABS && (org[0] + tx < 0 || org[0] + tx >= nx)) continue;   // outside the box
         if (DET) {
             const unsigned long long h[3] = {jth[li], jth[JC + li], jth[2 * JC + li]};
             const int l[3] = {jtl[li], jtl[JC + li], jtl[2 * JC + li]};
@@ -656,6 +667,7 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
         const int off[3] = {0, 0, 0};
         gather6(st, off,
                 [&](int comp, int ix, int iy, int iz, int da, int db, int dc) {
+                    if (g.absorb_x && (ix + da < 0 || ix + da >= nx)) return 0.0;
                     return a.EB[comp][wrapi(ix + da, nx) +
                                       nx * (wrapi(iy + db, ny) + ny * wrapi(iz + dc, nz))];
                 },
@@ -668,6 +680,7 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) c1[d] = (int)floor(x1[d]);
         vb_move(x0, x1, c0, c1, a.sp.jc, [&](int d, int i, int j, int k, double vv) {
+            if (g.absorb_x && (i < 0 || i >= nx)) return;      // outside the box
             const int gi = wrapi(i, nx) + nx * (wrapi(j, ny) + ny * wrapi(k, nz));
             if (a.det.hi[0]) {
                 unsigned long long h;
@@ -679,7 +692,8 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
                 unsafeAtomicAdd(&a.J[d][gi], vv);
             }
         });
-        const double xw[3] = {wrap_coord(x1[0], L[0]), wrap_coord(x1[1], L[1]),
+        const bool removed = g.absorb_x && !(x1[0] >= 0.0 && x1[0] < L[0] - 1.0);
+        const double xw[3] = {removed ? -1.0 : wrap_coord(x1[0], L[0]), wrap_coord(x1[1], L[1]),
                               wrap_coord(x1[2], L[2])};
         a.dst.x[ip] = xw[0];
         a.dst.y[ip] = xw[1];
@@ -687,26 +701,46 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
         a.dst.ux[ip] = u[0];
         a.dst.uy[ip] = u[1];
         a.dst.uz[ip] = u[2];
-        if (a.keys) a.keys[ip] = sort_key_rt(g, xw);
+        if (a.keys) a.keys[ip] = removed ? (unsigned)g.ncell : sort_key_rt(g, xw);
         cnt += 1;
     }
     if (cnt) atomicAdd(a.nfar, cnt);
 }
 
+// Absorbing x boundaries are compiled for these (S, h) pairs only.
+template <int S, int H>
+constexpr bool abs_supported() {
+    return (S == 2 || S == 4) && (H == 1 || H == 2);
+}
+
 template <int S, int H>
 hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
     const bool det = args.det.hi[0] != nullptr;
+    if constexpr (abs_supported<S, H>()) {
+        if (args.g.absorb_x) {
+            if (det) return hipErrorInvalidValue;
+            if (args.perm)
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, true>),
+                                   dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+            else
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, true>),
+                                   dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+            return hipGetLastError();
+        }
+    } else {
+        if (args.g.absorb_x) return hipErrorInvalidValue;
+    }
     if (args.perm && det)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, true>), dim3(args.g.nsc), dim3(kBlock),
-                           0, s, args);
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, true, false>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, args);
     else if (args.perm)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false>), dim3(args.g.nsc),
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, false>), dim3(args.g.nsc),
                            dim3(kBlock), 0, s, args);
     else if (det)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, true>), dim3(args.g.nsc),
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, true, false>), dim3(args.g.nsc),
                            dim3(kBlock), 0, s, args);
     else
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false>), dim3(args.g.nsc),
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, false>), dim3(args.g.nsc),
                            dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }

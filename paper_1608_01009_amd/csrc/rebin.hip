@@ -40,7 +40,9 @@ __global__ void __launch_bounds__(kBlock) key_kernel(Geom g, int n, const double
         bool ok = isfinite(ux[i]) && isfinite(uy[i]) && isfinite(uz[i]);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const bool in = p[d] >= 0.0 && p[d] < (double)g.n[d];   // false for NaN
+            // absorbing x: particles live in [0, n0 - 1)
+            const double hi = (d == 0 && g.absorb_x) ? (double)(g.n[0] - 1) : (double)g.n[d];
+            const bool in = p[d] >= 0.0 && p[d] < hi;   // false for NaN
             ok = ok && in;
             c[d] = in ? (int)floor(p[d]) : 0;
         }
@@ -49,6 +51,14 @@ __global__ void __launch_bounds__(kBlock) key_kernel(Geom g, int n, const double
         const int loc = c[0] % S + S * (c[1] % S + S * (c[2] % S));
         key[i] = (unsigned)(sc * S3 + loc);
     }
+}
+
+// Removed particles (key ncell) follow every supercell: their new slots
+// [sc_off[nsc], n) take them in sorted (previous) order.
+__global__ void __launch_bounds__(kBlock) tail_kernel(const unsigned* perm_sorted, int n,
+                                                     const int* sc_end, unsigned* out) {
+    for (int i = *sc_end + blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        out[i] = perm_sorted ? perm_sorted[i] : (unsigned)i;
 }
 
 template <int BITS>
@@ -324,8 +334,9 @@ int grid_for(int64_t n) {
     return b < 1 ? 1 : (int)b;
 }
 
+// With absorbing x a removed particle has key ncell (after every cell).
 int key_bits(const Geom& g) {
-    unsigned maxkey = (unsigned)g.ncell - 1u;
+    unsigned maxkey = (unsigned)g.ncell - (g.absorb_x ? 0u : 1u);
     int b = 0;
     while (b < 32 && (maxkey >> b) != 0u) ++b;
     return b;
@@ -449,6 +460,9 @@ hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const P
                        S3, g.nsc, sc_off);
     hipLaunchKernelGGL(interleave_kernel, dim3(g.nsc), dim3(kBlock), 0, s, kin, vin, sc_off, S3,
                        perm);
+    if (g.absorb_x)
+        hipLaunchKernelGGL(tail_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, vin, n,
+                           sc_off + g.nsc, perm);
     return hipGetLastError();
 }
 

@@ -25,6 +25,10 @@ PIC_FP64 = 0
 PIC_FP32_MIXED = 1
 _PRECISION = {"fp64": PIC_FP64, "mixed": PIC_FP32_MIXED, PIC_FP64: PIC_FP64,
               PIC_FP32_MIXED: PIC_FP32_MIXED}
+PIC_BC_PERIODIC = 0
+PIC_BC_ABSORBING = 1
+_BC = {"periodic": PIC_BC_PERIODIC, "absorbing": PIC_BC_ABSORBING, PIC_BC_PERIODIC: 0,
+       PIC_BC_ABSORBING: 1}
 PIC_ENOMEM = -2
 PIC_EDEVICE = -3
 PIC_ECAPACITY = -4
@@ -36,14 +40,14 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
 # the entry points declared in include/pic.h
 ABI_SYMBOLS = ("pic_create", "pic_load_particles", "pic_set_fields", "pic_step",
                "pic_get_fields", "pic_get_particles", "pic_diagnostics", "pic_enable_timers",
-               "pic_get_timers", "pic_get_counters", "pic_record", "pic_backward",
+               "pic_get_timers", "pic_get_counters", "pic_record", "pic_backward", "pic_set_laser",
                "pic_last_error", "pic_destroy")
 
 
 class PicGrid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("supercell", C.c_int32), ("rebin_every", C.c_int32),
                 ("halo", C.c_int32), ("precision", C.c_int32), ("deterministic_j", C.c_int32),
-                ("reserved", C.c_int32 * 2), ("stream", C.c_void_p)]
+                ("bc_x", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
 
 
 class PicSpecies(C.Structure):
@@ -91,6 +95,7 @@ def library():
         L.pic_get_timers.argtypes = [V, D]
         L.pic_get_counters.argtypes = [V, C.POINTER(C.c_int64)]
         L.pic_record.argtypes = [V, C.c_int32]
+        L.pic_set_laser.argtypes = [V, C.c_double, C.c_double, C.c_double, C.c_int32]
         L.pic_backward.argtypes = [V, C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V)]
         L.pic_last_error.argtypes = [V]
         L.pic_last_error.restype = C.c_char_p
@@ -135,7 +140,7 @@ def _torch_stream():
 
 def pic_create(n: Sequence[int], dx: Sequence[float], dt: float, species, *, supercell: int = 4,
                rebin_every: int = 20, halo: int = 0, stream=None, precision="fp64",
-               deterministic_j: bool = False):
+               deterministic_j: bool = False, bc_x="periodic"):
     """``species``: sequence of ``(charge, mass, weight, capacity)``.
     ``stream``: None (library-owned stream), ``"torch"`` (torch's current
     stream) or a raw ``hipStream_t`` integer.  ``precision``: "fp64" or
@@ -150,6 +155,7 @@ def pic_create(n: Sequence[int], dx: Sequence[float], dt: float, species, *, sup
     g.halo = int(halo)
     g.precision = _PRECISION[precision] if precision in _PRECISION else int(precision)
     g.deterministic_j = int(deterministic_j)
+    g.bc_x = _BC[bc_x] if bc_x in _BC else int(bc_x)
     if stream == "torch":
         stream = _torch_stream()
     g.stream = stream
@@ -176,6 +182,11 @@ def pic_set_fields(ctx, EB: Sequence, ncell: Optional[int] = None):
     nc = ncell if ncell is not None else int(EB[0].shape[0])
     arr = (C.c_void_p * 6)(*[_addr(a, nc, np.float64) for a in EB])
     _check(ctx, library().pic_set_fields(ctx, arr))
+
+
+def pic_set_laser(ctx, amplitude: float, omega: float, duration: float, plane: int):
+    _check(ctx, library().pic_set_laser(ctx, float(amplitude), float(omega), float(duration),
+                                        int(plane)))
 
 
 def pic_step(ctx, n_steps: int = 1):
@@ -289,22 +300,25 @@ class Simulation:
     """Owning convenience wrapper around one context."""
 
     def __init__(self, n, dx, dt, species, *, supercell=4, rebin_every=20, halo=0, stream=None,
-                 precision="fp64", deterministic_j=False):
+                 precision="fp64", deterministic_j=False, bc_x="periodic"):
         self.n = tuple(int(v) for v in n)
         self.ncell = self.n[0] * self.n[1] * self.n[2]
         self.species = [tuple(s) for s in species]
         self.precision = precision
         self.ctx = pic_create(n, dx, dt, species, supercell=supercell, rebin_every=rebin_every,
                               halo=halo, stream=stream, precision=precision,
-                              deterministic_j=deterministic_j)
+                              deterministic_j=deterministic_j, bc_x=bc_x)
 
     @classmethod
     def from_workload(cls, wl, capacity_factor=1.0, **kw):
         species = [(s.charge, s.mass, s.weight, int(s.n * capacity_factor)) for s in wl.species]
-        sim = cls(wl.n, wl.dx, wl.dt, species, supercell=wl.S, rebin_every=wl.R, **kw)
+        bc = getattr(wl, "bc_x", "periodic")
+        sim = cls(wl.n, wl.dx, wl.dt, species, supercell=wl.S, rebin_every=wl.R, bc_x=bc, **kw)
         for i, s in enumerate(wl.species):
             sim.load_particles(i, *s.arrays())
         sim.set_fields(wl.fields)
+        if getattr(wl, "laser", None) is not None:
+            sim.set_laser(*wl.laser)
         return sim
 
     def load_particles(self, species, x, y, z, ux, uy, uz, ids=None):
@@ -339,6 +353,9 @@ class Simulation:
         if code not in (PIC_OK, PIC_ECAPACITY):
             _check(self.ctx, code)
         return int(n.value)
+
+    def set_laser(self, amplitude, omega, duration, plane):
+        pic_set_laser(self.ctx, amplitude, omega, duration, plane)
 
     def record(self, checkpoint_every=20):
         pic_record(self.ctx, checkpoint_every)

@@ -68,6 +68,8 @@ class Workload:
     species: List[Species]
     fields: List[np.ndarray]            # Ex, Ey, Ez, Bx, By, Bz (flat, x-fastest)
     meta: dict = field(default_factory=dict)
+    bc_x: str = "periodic"              # or "absorbing"
+    laser: Optional[Tuple[float, float, float, int]] = None   # (E0, omega, T, plane)
 
     @property
     def ncells(self) -> int:
@@ -196,6 +198,47 @@ def config5(amplitudes: Optional[np.ndarray] = None) -> Workload:
     wl.fields[0] = np.ascontiguousarray(np.broadcast_to(prof[None, None, :], (nz, ny, nx)).ravel())
     wl.meta["amplitudes"] = a.tolist()
     return wl
+
+
+def laser_slab(n=(256, 128, 128), slab=(96, 224), ppc=8, seed=1003, a0=1.0, wavelength=32.0,
+               envelope_steps=200, plane=2, density=0.5, S=4, R=20, steps=1000,
+               name="laser-slab-256x128x128") -> Workload:
+    """Laser-plasma slab: absorbing x boundaries, periodic y and z; cold
+    electrons and protons (mass 1836) at ``ppc`` particles per cell each, at
+    the same positions (a neutral start, E = B = 0), filling the cells
+    slab[0] <= x < slab[1] with density ``density`` times the critical
+    density of the laser (n_crit = omega^2 with m_e = e = 1); a linearly
+    polarised (E_y) laser of wavelength ``wavelength`` cells, normalised
+    amplitude a0 (E0 = a0 omega) and a sin^2 envelope ``envelope_steps`` steps
+    long, launched from the node plane x = ``plane``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = n
+    sub = (slab[1] - slab[0], ny, nz)
+    x, y, z = uniform_positions(rng, sub, ppc)
+    x = x + float(slab[0])
+    dt = courant_dt()
+    omega = 2.0 * math.pi / wavelength
+    n0 = density * omega * omega
+    w = n0 / ppc
+    zeros = np.zeros(x.shape[0])
+    species = []
+    for q, m in (ELECTRON, PROTON):
+        species.append(Species(q, m, w, x.copy(), y.copy(), z.copy(), zeros.copy(),
+                               zeros.copy(), zeros.copy()))
+    nc = nx * ny * nz
+    fields = [np.zeros(nc) for _ in range(6)]
+    return Workload(name, tuple(n), (1.0, 1.0, 1.0), dt, S, R, steps, species, fields,
+                    meta=dict(ppc=ppc, seed=seed, slab=tuple(slab), a0=a0,
+                              wavelength=wavelength, density=density, n0=n0),
+                    bc_x="absorbing",
+                    laser=(a0 * omega, omega, envelope_steps * dt, int(plane)))
+
+
+def config3() -> Workload:
+    """Laser-plasma slab on 256 x 128 x 128 cells (absorbing x), electrons and
+    protons at 8 per cell each in 96 <= x < 224 (33,554,432 particles), 0.5 n_crit,
+    a0 = 1, wavelength 32 cells, 200-step sin^2 envelope, 1000 steps."""
+    return laser_slab()
 
 
 def scaled(cfg: int, n, ppc, seed=7, **kw) -> Workload:

@@ -60,6 +60,10 @@ def _create(**kw):
     (dict(precision="mixed", n=(2048, 8, 8)), "1024 cells"),
     (dict(species=[(-1.0, 1e-280, 0.1, 10)]), "charge dt"),
     (dict(species=[]), "n_species"),
+    (dict(bc_x=2), "bc_x"),
+    (dict(bc_x="absorbing", precision="mixed"), "PIC_BC_ABSORBING"),
+    (dict(bc_x="absorbing", deterministic_j=True), "PIC_BC_ABSORBING"),
+    (dict(bc_x="absorbing", supercell=1), "supercell 2 or 4"),
 ])
 def test_create_rejects_invalid_arguments(kw, needle):
     from paper_1608_01009_amd import pic

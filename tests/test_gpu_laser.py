@@ -1,0 +1,143 @@
+"""GPU tests of the laser-plasma extensions (absorbing x boundaries, particle
+removal, laser current sheet) against the oracle.
+
+* one step from an identical state, the protocol and tolerances of the
+  periodic parity tests, on a small laser slab (64 x 8 x 8 cells, electrons
+  and protons in 24 <= x < 56, wavelength 16 cells, a0 = 1) with a third
+  species of relativistic electrons leaving through both x boundaries: at
+  the start, around a re-sort that drops removed particles, and while the
+  laser pulse crosses the slab; removed particles (x = -1) and the stored
+  order agree bit for bit;
+* the laser in vacuum: fields after 300 steps against the oracle's;
+* the diagnostics (Gauss residual at the inside nodes, charge of the
+  particles inside) and the error codes of the boundary and source settings.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_01009_amd import pic
+from paper_1608_01009_amd import workloads as W
+
+from gpu_parity_util import KEYS, compare, log, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_slab(seed=21):
+    wl = W.laser_slab(n=(64, 8, 8), slab=(24, 56), ppc=2, seed=seed, wavelength=16.0,
+                      name="laser-slab-64x8x8")
+    rng = np.random.default_rng(seed)
+    nb = 512
+    x = np.concatenate([rng.uniform(1.0, 4.0, nb // 2), rng.uniform(58.0, 62.9, nb // 2)])
+    ux = np.concatenate([rng.uniform(-3.0, -0.5, nb // 2), rng.uniform(0.5, 3.0, nb // 2)])
+    beam = W.Species(-1.0, 1.0, 0.01, x, rng.uniform(0, 8, nb), rng.uniform(0, 8, nb), ux,
+                     rng.normal(scale=0.3, size=nb), rng.normal(scale=0.3, size=nb))
+    wl.species.append(beam)
+    return wl
+
+
+def _oracle(wl, F, P, k):
+    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+                         S=wl.S, R=wl.R, absorb_x=True, laser=wl.laser)
+    o.set_state([[p[k_][:p["n"]] for k_ in KEYS] for p in P], F[:6], k % wl.R, step_count=k)
+    return o
+
+
+def _state(sim, ns):
+    return sim.fields(), [sim.particles(s) for s in range(ns)]
+
+
+def test_laser_slab_one_step_parity():
+    wl = _small_slab()
+    ns = len(wl.species)
+    sim = pic.Simulation.from_workload(wl)
+    at = 0
+    removed = 0
+    for k in (0, 1, 19, 20, 39, 60, 100, 159, 160):
+        if k > at:
+            sim.step(k - at)
+            at = k
+        F0, P0 = _state(sim, ns)
+        sim.step(1)
+        at += 1
+        F1, P1 = _state(sim, ns)
+        o = _oracle(wl, F0, P0, k)
+        o.step(1)
+        log(f"  step {k} -> {k + 1}: counts {[p['n'] for p in P1]}, removed marked "
+            f"{[int(np.sum(p['x'][:p['n']] < 0)) for p in P1]}")
+        rep = compare(F1, P1, o, wl.n, tag=f"slab step {k}")
+        removed += int(np.sum(P1[2]["x"][:P1[2]["n"]] < 0))
+        log(f"    {rep}")
+    # particles left through both boundaries and the re-sorts dropped them
+    assert sim.particles(2)["n"] < 512
+    assert removed > 0
+    # the pulse reached the slab: the electrons there moved
+    ux = sim.particles(0)["uy"]
+    assert np.max(np.abs(ux)) > 0.05
+    sim.close()
+
+
+def test_laser_in_vacuum_matches_oracle():
+    n = (96, 4, 4)
+    wl = W.laser_slab(n=n, slab=(40, 44), ppc=1, wavelength=16.0, name="vacuum")
+    for s in wl.species:
+        for a in ("x", "y", "z", "ux", "uy", "uz"):
+            setattr(s, a, getattr(s, a)[:0].copy())
+    sim = pic.Simulation.from_workload(wl)
+    sim.step(300)
+    F = sim.fields()
+    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+                         S=wl.S, R=wl.R, absorb_x=True, laser=wl.laser)
+    for s in range(2):
+        o.load_particles(s, *[np.zeros(0)] * 6)
+    o.set_fields(wl.fields)
+    o.step(300)
+    worst = 0.0
+    for c in range(9):
+        worst = max(worst, max_rel(F[c], o.F[c]))
+    log(f"  vacuum laser, 300 steps: max rel {worst:.2e}, "
+        f"exact {np.mean([np.array_equal(F[c], o.F[c]) for c in range(9)]):.2f}")
+    assert worst <= 1e-14
+    assert np.max(np.abs(F[1])) > 0.3 * wl.laser[0]      # the pulse is in the box
+    sim.close()
+
+
+def test_diagnostics_and_error_codes():
+    wl = _small_slab(seed=23)
+    ns = len(wl.species)
+    sim = pic.Simulation.from_workload(wl)
+    d0 = sim.diagnostics()
+    q0 = d0[3]
+    sim.step(45)
+    d = sim.diagnostics()
+    P = [sim.particles(s) for s in range(ns)]
+    live = [int(np.sum(p["x"][:p["n"]] >= 0)) for p in P]
+    q = sum(s.charge * s.weight * nl for s, nl in zip(wl.species, live))
+    assert d[3] == pytest.approx(q, rel=1e-12, abs=1e-12)
+    assert q != q0                                       # beam charge left the box
+    rho_scale = 2 * wl.meta["n0"]
+    assert d[4] <= 1e-12 * rho_scale                     # Gauss at the inside nodes
+    assert d[5] <= 1e-13
+    # settings
+    with pytest.raises(pic.PicError) as e:
+        sim.set_laser(0.1, 0.3, 10.0, 0)                 # plane on the boundary
+    assert e.value.code == pic.PIC_EINVAL
+    with pytest.raises(pic.PicError) as e:
+        sim.set_laser(0.1, 0.3, 0.0, 5)                  # duration
+    assert e.value.code == pic.PIC_EINVAL
+    x = wl.species[0].x.copy()
+    x[0] = 63.0                                          # n0 - 1: outside the particle range
+    sp = wl.species[0]
+    with pytest.raises(pic.PicError) as e:
+        sim.load_particles(0, x, sp.y, sp.z, sp.ux, sp.uy, sp.uz)
+    assert e.value.code == pic.PIC_EINVAL
+    with pytest.raises(pic.PicError) as e:
+        sim.record(5)
+    assert e.value.code == pic.PIC_EINVAL
+    sim.close()
+    per = pic.Simulation((8, 8, 8), (1.0, 1.0, 1.0), 0.25, [(-1.0, 1.0, 1.0, 10)])
+    with pytest.raises(pic.PicError) as e:
+        per.set_laser(0.1, 0.3, 10.0, 3)
+    assert e.value.code == pic.PIC_EINVAL
+    per.close()
