@@ -123,6 +123,53 @@ def mixed_leg(wl, args):
             "gauss_drift": d[4]}
 
 
+def laser_leg():
+    """The laser-plasma slab (256 x 128 x 128 cells, absorbing x, electrons and
+    protons at 8 per cell each in 96 <= x < 224: 33,554,432 particles, a0 = 1,
+    wavelength 32 cells, 200-step envelope): its 1000 steps from t = 0, timed
+    as one run (a small context of the same kind runs first to load the
+    kernels).  value = particles at the start x steps / wall time."""
+    from paper_1608_01009_amd import pic
+    from paper_1608_01009_amd import workloads as W
+    import torch
+    warm = W.laser_slab(n=(64, 8, 8), slab=(24, 56), ppc=2, wavelength=16.0, name="warm")
+    ws = pic.Simulation.from_workload(warm)
+    ws.step(25)
+    ws.close()
+    wl = W.config3()
+    n0 = wl.nparticles
+    log(f"laser slab: {wl.name}, {n0} particles, loading")
+    sim = pic.Simulation.from_workload(wl)
+    pic.pic_enable_timers(sim.ctx, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(wl.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = pic.pic_get_timers(sim.ctx)
+    counts = sim.counts()
+    d = sim.diagnostics()
+    sim.close()
+    push_us = tm[0] / max(tm[1], 1) * 1e3
+    # per launch (one species): its particles read and written once (96 B
+    # each) and the E/B tiles and J of the slab's cells (72 B per cell)
+    slab_cells = (wl.meta["slab"][1] - wl.meta["slab"][0]) * wl.n[1] * wl.n[2]
+    bytes_launch = (n0 // 2) * 96 + slab_cells * 72
+    achieved = bytes_launch / (push_us * 1e-6) / 1e9
+    log(f"laser slab: wall {wall*1e3:.1f} ms for {wl.steps} steps ({wall*1e3/wl.steps:.3f} ms/step); "
+        f"push+deposit {push_us:.1f} us per species launch; particles left {counts}; "
+        f"gauss drift {d[4]:.2e}")
+    return {"workload": wl.name, "value": n0 * wl.steps / wall, "unit": "particle updates/s",
+            "steps": wl.steps, "ms_per_step": wall * 1e3 / wl.steps, "particles": n0,
+            "particles_at_end": counts, "dtype": "f64",
+            "roofline": {"bound": "hbm", "kernel": "push_deposit_kernel<4, 1, false, false, true>",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_launch": bytes_launch,
+                         "avg_launch_us": push_us},
+            "gauss_drift": d[4]}
+
+
 def adjoint_leg():
     """Gradient of the final field energy through 400 recorded steps of the
     32^3 / 16 ppc eight-mode workload (deterministic J, checkpoints every 20
@@ -165,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-mixed leg (same workload, PIC_FP32_MIXED)")
+    ap.add_argument("--no-laser", action="store_true",
+                    help="skip the laser-plasma slab leg (1000 steps, 33.6 M particles)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint leg (gradient through 400 recorded steps)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -250,6 +299,8 @@ def main():
     }
     if not args.no_mixed:
         rec["fp32_mixed"] = mixed_leg(wl, args)
+    if not args.no_laser:
+        rec["laser_slab"] = laser_leg()
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_leg()
     if args.copy_calibration_mib > 0:
