@@ -403,6 +403,33 @@ push_deposit_kernel(const PDArgs a) {
     const int wv = threadIdx.x >> 6;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
+    // software pipeline: the next particle's state is loaded one iteration
+    // ahead; the first particle's loads are issued before the tile loads so
+    // that the two latencies overlap
+    double nxt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // Particle arrays are addressed with 32-bit byte offsets from the scalar
+    // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
+    // six loads and six stores of a particle share one offset register.
+    auto ld6 = [&](unsigned j, double o[6]) {
+        const unsigned b = j * 8u;
+        o[0] = *(const double*)((const char*)a.src.x + b);
+        o[1] = *(const double*)((const char*)a.src.y + b);
+        o[2] = *(const double*)((const char*)a.src.z + b);
+        o[3] = *(const double*)((const char*)a.src.ux + b);
+        o[4] = *(const double*)((const char*)a.src.uy + b);
+        o[5] = *(const double*)((const char*)a.src.uz + b);
+    };
+    // GATHER: the re-sort order is read two iterations ahead of the data it
+    // addresses, so that issuing the next particle's loads never waits on a
+    // just-issued order load (the vector memory counter completes in issue
+    // order, and such a wait would also wait for this iteration's stores).
+    unsigned pj = 0;
+    {
+        const int ip = p0 + (int)threadIdx.x;
+        if (ip < p1) ld6(GATHER ? a.perm[ip] : (unsigned)ip, nxt);
+        if (GATHER && ip + kBlock < p1) pj = a.perm[ip + kBlock];
+    }
+
     // E/B tile: one wrapped global index per node, shared by the six
     // components (tile coordinates lie within one period of [0, n))
     for (int r = threadIdx.x; r < T3; r += kBlock) {
@@ -465,25 +492,6 @@ push_deposit_kernel(const PDArgs a) {
     };
 
     int qcount = 0;  // wave-uniform
-    // software pipeline: the next particle's state is loaded one iteration ahead
-    double nxt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    // Particle arrays are addressed with 32-bit byte offsets from the scalar
-    // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
-    // six loads and six stores of a particle share one offset register.
-    auto ld6 = [&](int ip, double o[6]) {
-        const unsigned j = GATHER ? a.perm[ip] : (unsigned)ip;
-        const unsigned b = j * 8u;
-        o[0] = *(const double*)((const char*)a.src.x + b);
-        o[1] = *(const double*)((const char*)a.src.y + b);
-        o[2] = *(const double*)((const char*)a.src.z + b);
-        o[3] = *(const double*)((const char*)a.src.ux + b);
-        o[4] = *(const double*)((const char*)a.src.uy + b);
-        o[5] = *(const double*)((const char*)a.src.uz + b);
-    };
-    {
-        const int ip = p0 + (int)threadIdx.x;
-        if (ip < p1) ld6(ip, nxt);
-    }
     for (int pb = p0; pb < p1; pb += kBlock) {
         const int ip = pb + (int)threadIdx.x;
         const bool valid = ip < p1;
@@ -491,7 +499,8 @@ push_deposit_kernel(const PDArgs a) {
         double u[3] = {nxt[3], nxt[4], nxt[5]};
         {
             const int in = ip + kBlock;
-            if (in < p1) ld6(in, nxt);
+            if (in < p1) ld6(GATHER ? pj : (unsigned)in, nxt);
+            if (GATHER && in + kBlock < p1) pj = a.perm[in + kBlock];
         }
         bool crosser = false, far = false;
         double x1[3] = {0.0, 0.0, 0.0};
@@ -824,7 +833,9 @@ hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src
                              unsigned* far_n_next, const DetJ& det, hipStream_t s) {
     const PDArgs args = make_args(g, sp, src, dst, perm, keys, nullptr, f, J, err, nfar, far_q,
                                   far_n, far_n_next, det);
-    hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
+    // far movers are few (tens per step); 64 workgroups keep the launch
+    // short and still cover 32 K of them per pass of the grid-stride loop
+    hipLaunchKernelGGL(far_kernel, dim3(64), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
 

@@ -247,39 +247,50 @@ __global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
     const unsigned kb = (unsigned)sc * (unsigned)S3;
     for (int i = s0 + threadIdx.x; i < s1; i += kBlock) atomicAdd(&cnt[key[i] - kb], 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = s0, mx = 0;
-        for (int l = 0; l < S3; ++l) {
-            cst[l] = run;
-            run += cnt[l];
-            mx = cnt[l] > mx ? cnt[l] : mx;
+    const int nwords = (S3 + 63) / 64;
+    if (threadIdx.x < 64) {
+        // wave 0: cell starts (exclusive prefix of the counts) and the
+        // largest count, 64 cells at a time
+        const int lane = threadIdx.x;
+        int carry = s0, mx = 0;
+        for (int w = 0; w < nwords; ++w) {
+            const int l = 64 * w + lane;
+            const int c = l < S3 ? cnt[l] : 0;
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            if (l < S3) cst[l] = carry + incl - c;
+            carry += __shfl(incl, 63, 64);
+            mx = c > mx ? c : mx;
         }
-        maxc_s = mx;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int t = __shfl_xor(mx, o, 64);
+            mx = t > mx ? t : mx;
+        }
+        if (lane == 0) maxc_s = mx;
+        // round masks (cells with more than r particles, one ballot per 64
+        // cells) and round starts (prefix of the round sizes)
+        if (mx <= kMaxRounds) {
+            int run = 0;
+            for (int r = 0; r < mx; ++r) {
+                if (lane == 0) rstart[r] = run;
+                for (int w = 0; w < nwords; ++w) {
+                    const int l = 64 * w + lane;
+                    const unsigned long long m = __ballot(l < S3 && cnt[l] > r);
+                    if (lane == 0) rmask[r][w] = m;
+                    run += __popcll(m);
+                }
+            }
+            if (lane == 0) rstart[mx] = run;
+        }
     }
     __syncthreads();
     const int maxc = maxc_s;
-    const int nwords = (S3 + 63) / 64;
     if (maxc <= kMaxRounds) {
-        // round masks, then round starts (prefix of round sizes)
-        for (int r = threadIdx.x; r < maxc; r += kBlock) {
-            for (int w = 0; w < nwords; ++w) {
-                unsigned long long m = 0ull;
-                const int lend = (S3 - 64 * w) < 64 ? (S3 - 64 * w) : 64;
-                for (int b = 0; b < lend; ++b)
-                    if (cnt[64 * w + b] > r) m |= 1ull << b;
-                rmask[r][w] = m;
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int run = 0;
-            for (int r = 0; r < maxc; ++r) {
-                rstart[r] = run;
-                for (int w = 0; w < nwords; ++w) run += __popcll(rmask[r][w]);
-            }
-            rstart[maxc] = run;
-        }
-        __syncthreads();
         for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
             const int loc = (int)(key[i] - kb);
             const int rank = i - cst[loc];
