@@ -453,6 +453,26 @@ push_mixed_kernel(const MArgs a) {
     const int wv = threadIdx.x >> 6;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
+    // the first particle's loads go out before the tile loads: the two
+    // latencies overlap
+    unsigned ncell = 0u;
+    float nxt[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto ld7 = [&](int ip, unsigned& cp, float o[6]) {
+        const unsigned j = GATHER ? a.perm[ip] : (unsigned)ip;
+        const unsigned b = j * 4u;
+        cp = *(const unsigned*)((const char*)a.src.cell + b);
+        o[0] = *(const float*)((const char*)a.src.ox + b);
+        o[1] = *(const float*)((const char*)a.src.oy + b);
+        o[2] = *(const float*)((const char*)a.src.oz + b);
+        o[3] = *(const float*)((const char*)a.src.ux + b);
+        o[4] = *(const float*)((const char*)a.src.uy + b);
+        o[5] = *(const float*)((const char*)a.src.uz + b);
+    };
+    {
+        const int ip = p0 + (int)threadIdx.x;
+        if (ip < p1) ld7(ip, ncell, nxt);
+    }
+
     for (int r = threadIdx.x; r < T3; r += kBlock) {
         const int tz = r / T2, ty = (r / T) % T, tx = r % T;
         const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
@@ -499,23 +519,6 @@ push_mixed_kernel(const MArgs a) {
     };
 
     int qcount = 0;
-    unsigned ncell = 0u;
-    float nxt[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    auto ld7 = [&](int ip, unsigned& cp, float o[6]) {
-        const unsigned j = GATHER ? a.perm[ip] : (unsigned)ip;
-        const unsigned b = j * 4u;
-        cp = *(const unsigned*)((const char*)a.src.cell + b);
-        o[0] = *(const float*)((const char*)a.src.ox + b);
-        o[1] = *(const float*)((const char*)a.src.oy + b);
-        o[2] = *(const float*)((const char*)a.src.oz + b);
-        o[3] = *(const float*)((const char*)a.src.ux + b);
-        o[4] = *(const float*)((const char*)a.src.uy + b);
-        o[5] = *(const float*)((const char*)a.src.uz + b);
-    };
-    {
-        const int ip = p0 + (int)threadIdx.x;
-        if (ip < p1) ld7(ip, ncell, nxt);
-    }
     for (int pb = p0; pb < p1; pb += kBlock) {
         const int ip = pb + (int)threadIdx.x;
         const bool valid = ip < p1;
