@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "push_deposit_64c_50ppc_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1608_01009_amd", "csrc", "push_deposit.hip")
 COUNTERS_MIXED = os.path.join(ROOT, "profiles", "push_mixed_64c_50ppc_counters.md")
+COUNTERS_SLAB = os.path.join(ROOT, "profiles", "push_deposit_laser_slab_counters.md")
 KERNEL_SRC_MIXED = os.path.join(ROOT, "paper_1608_01009_amd", "csrc", "push_mixed.hip")
 
 
@@ -164,7 +165,8 @@ def laser_leg():
             "particles_at_end": counts, "dtype": "f64",
             "roofline": {"bound": "hbm", "kernel": "push_deposit_kernel<4, 1, false, false, true>",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(COUNTERS_SLAB, KERNEL_SRC),
                          "algorithmic_bytes_per_launch": bytes_launch,
                          "avg_launch_us": push_us},
             "gauss_drift": d[4]}
