@@ -94,6 +94,7 @@ struct pic_ctx {
     int* far_q = nullptr;          // far-mover queue (capacity of the largest species)
     unsigned* far_n = nullptr;     // two queue counters, used alternately by launches
     int far_phase = 0;
+    int pair_phase = 0;            // counters far_n[4..7] of the two-species launch
     unsigned* h_err = nullptr;
     double* rho = nullptr;
     double* tmp = nullptr;
@@ -313,7 +314,59 @@ int step_once(pic_ctx* c) {
     const Fields fo{{c->Eo[0], c->Eo[1], c->Eo[2]}, {c->Bo[0], c->Bo[1], c->Bo[2]}};
     double* const* Jd = c->J[c->jdep];
     const bool sort_after = (c->steps_since_sort + 1 == c->R);
+    // two species over one tile load per supercell
+    const bool pair = c->sp.size() == 2 && c->precision == PIC_FP64 && c->sp[0].n > 0 &&
+                      c->sp[1].n > 0 && c->sp[0].pending == c->sp[1].pending &&
+                      push_deposit_pair_supported(c->g.S, c->g.h, c->det.hi[0] != nullptr);
+    if (pair) {
+        SpeciesC spc[2];
+        Parts src[2], dst[2];
+        const unsigned* perm[2];
+        unsigned* keys[2];
+        const int* off[2];
+        int* fq[2];
+        unsigned* fn[2];
+        unsigned* fnn[2];
+        for (int k = 0; k < 2; ++k) {
+            SpeciesState& s = c->sp[k];
+            spc[k] = s.c;
+            src[k] = s.buf[s.cur];
+            dst[k] = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
+            perm[k] = s.pending ? s.perm : nullptr;
+            keys[k] = sort_after ? s.keys : nullptr;
+            off[k] = s.sc_off;
+            fq[k] = c->far_q + (k == 0 ? 0 : c->sp[0].capacity);
+            fn[k] = c->far_n + 4 + 2 * k + c->pair_phase;
+            fnn[k] = c->far_n + 4 + 2 * k + (1 - c->pair_phase);
+        }
+        const bool pend = c->sp[0].pending;
+        {
+            Timed t(c, pend ? ST_PUSH_PERM : ST_PUSH);
+            HIPCHK(c, launch_push_deposit_pair(c->g, spc, src, dst, perm, keys, off, f, Jd,
+                                               c->d_err, c->d_nfar, fq, fn, fnn, c->det,
+                                               c->stream));
+        }
+        {
+            Timed t(c, ST_FAR);
+            for (int k = 0; k < 2; ++k)
+                HIPCHK(c, launch_far_movers(c->g, spc[k], src[k], dst[k], perm[k], keys[k], f,
+                                            Jd, c->d_err, c->d_nfar, fq[k], fn[k], fnn[k],
+                                            c->det, c->stream));
+        }
+        c->pair_phase = 1 - c->pair_phase;
+        if (c->timers) (pend ? c->push_perm_launches : c->push_launches)++;
+        if (pend) {
+            Timed t(c, ST_SORT);
+            for (int k = 0; k < 2; ++k) {
+                SpeciesState& s = c->sp[k];
+                HIPCHK(c, launch_permute_ids(s.n, s.perm, src[k].id, dst[k].id, c->stream));
+                s.cur = 1 - s.cur;
+                s.pending = false;
+            }
+        }
+    }
     for (auto& s : c->sp) {
+        if (pair) break;
         if (s.n == 0) continue;
         const bool mixed = c->precision == PIC_FP32_MIXED;
         const Parts& src = s.buf[s.cur];
@@ -763,7 +816,12 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
             (e = dalloc(c, (void**)&st.perm, (size_t)q.capacity * sizeof(unsigned))) != hipSuccess)
             return cfail(hip_fail(c, e, "hipMalloc sc_off / keys / perm"));
     }
-    if ((e = dalloc(c, (void**)&c->far_q, (size_t)(maxcap > 0 ? maxcap : 1) * sizeof(int))) !=
+    // far-mover queue: one slot per particle of the largest species, or of
+    // the first two species together (their two-species launch fills two
+    // queues at once)
+    int64_t qcap = maxcap;
+    if (n_species == 2) qcap = species[0].capacity + species[1].capacity;
+    if ((e = dalloc(c, (void**)&c->far_q, (size_t)(qcap > 0 ? qcap : 1) * sizeof(int))) !=
         hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc far queue"));
     if (grid->deterministic_j) {

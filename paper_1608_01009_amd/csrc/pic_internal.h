@@ -126,6 +126,18 @@ hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src
                              unsigned* far_n_next, const DetJ& det, hipStream_t s);
 // det.hi[0] != NULL selects the deterministic accumulation into det (J is
 // then not touched; see launch_j_from_fixed).
+// Two species in one launch (arrays of two for every per-species argument):
+// one E/B tile load and one J flush per supercell for both, each species with
+// its own far-mover queue and counters; both read through a re-sort order or
+// neither.  Not with the deterministic J (push_deposit_pair_supported).
+bool push_deposit_pair_supported(int S, int h, bool det);
+hipError_t launch_push_deposit_pair(const Geom& g, const SpeciesC* sp, const Parts* src,
+                                    const Parts* dst, const unsigned* const* perm,
+                                    unsigned* const* keys, const int* const* sc_off,
+                                    const Fields& f, double* const J[3], unsigned* err,
+                                    unsigned long long* nfar, int* const* far_q,
+                                    unsigned* const* far_n, unsigned* const* far_n_next,
+                                    const DetJ& det, hipStream_t s);
 int push_deposit_lds_bytes(const Geom& g, bool det);
 bool push_deposit_supported(int S, int h);
 

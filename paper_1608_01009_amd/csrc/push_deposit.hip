@@ -77,6 +77,13 @@ struct PDArgs {
     DetJ det;              // deterministic mode: integer accumulators (hi[0] == nullptr: off)
 };
 
+// Arguments of NSP species pushed by one launch over one tile load per
+// supercell (geometry, fields, J, error word and det shared: those of s[0]).
+template <int NSP>
+struct PDMulti {
+    PDArgs s[NSP];
+};
+
 // One straight segment A->B inside the cell with integer corner `cell`
 // (Villasenor-Buneman): for J_d, the four edges of the d-directed cell edges
 // receive jc_d * delta_d * W with W = w_p w_r +- delta_p delta_r / 12 at the
@@ -352,9 +359,12 @@ __device__ __forceinline__ constexpr int jt_off(int j) {
 // ABS: absorbing x boundaries: lattice points outside 0 <= x < n0 read zero
 // and receive no current; a particle whose move ends outside 0 <= x < n0 - 1
 // is stored with x = -1 (removed) and later skipped.
-template <int S, int H, bool GATHER, bool DET, bool ABS>
+// NSP: species pushed one after the other over the same E/B tile and into the
+// same J tile (one tile load and one flush per supercell for all of them).
+template <int S, int H, bool GATHER, bool DET, bool ABS, int NSP>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
-push_deposit_kernel(const PDArgs a) {
+push_deposit_kernel(const PDMulti<NSP> m) {
+    const PDArgs& a = m.s[0];   // shared: geometry, fields, J, det, error word
     using EL = EBLayout<S, H>;
     constexpr int T = EL::T;           // E/B tile edge in nodes
     constexpr int T2 = T * T, T3 = T2 * T;
@@ -384,11 +394,20 @@ push_deposit_kernel(const PDArgs a) {
     __shared__ double qb[kWaves][6][QCAP];
 
     const int sc = xcd_block(blockIdx.x, gridDim.x);
-    const int p0 = a.sc_off[sc], p1 = a.sc_off[sc + 1];
-    if (p0 >= p1) return;  // empty supercell: uniform exit before any barrier
-    if (DET && p1 - p0 > kDetMaxPerSupercell) {
-        if (threadIdx.x == 0) atomicOr(a.err, ERR_DETCAP);
-        return;
+    {
+        // empty supercell: uniform exit before any barrier
+        bool any = false, over = false;
+#pragma unroll
+        for (int si = 0; si < NSP; ++si) {
+            const int q0 = m.s[si].sc_off[sc], q1 = m.s[si].sc_off[sc + 1];
+            any = any || q0 < q1;
+            over = over || (DET && q1 - q0 > kDetMaxPerSupercell);
+        }
+        if (!any) return;
+        if (over) {
+            if (threadIdx.x == 0) atomicOr(a.err, ERR_DETCAP);
+            return;
+        }
     }
 
     const Geom& g = a.g;
@@ -410,25 +429,27 @@ push_deposit_kernel(const PDArgs a) {
     // Particle arrays are addressed with 32-bit byte offsets from the scalar
     // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
     // six loads and six stores of a particle share one offset register.
-    auto ld6 = [&](unsigned j, double o[6]) {
+    auto ld6 = [&](const PDArgs& as, unsigned j, double o[6]) {
         const unsigned b = j * 8u;
-        o[0] = *(const double*)((const char*)a.src.x + b);
-        o[1] = *(const double*)((const char*)a.src.y + b);
-        o[2] = *(const double*)((const char*)a.src.z + b);
-        o[3] = *(const double*)((const char*)a.src.ux + b);
-        o[4] = *(const double*)((const char*)a.src.uy + b);
-        o[5] = *(const double*)((const char*)a.src.uz + b);
+        o[0] = *(const double*)((const char*)as.src.x + b);
+        o[1] = *(const double*)((const char*)as.src.y + b);
+        o[2] = *(const double*)((const char*)as.src.z + b);
+        o[3] = *(const double*)((const char*)as.src.ux + b);
+        o[4] = *(const double*)((const char*)as.src.uy + b);
+        o[5] = *(const double*)((const char*)as.src.uz + b);
     };
     // GATHER: the re-sort order is read two iterations ahead of the data it
     // addresses, so that issuing the next particle's loads never waits on a
     // just-issued order load (the vector memory counter completes in issue
     // order, and such a wait would also wait for this iteration's stores).
     unsigned pj = 0;
-    {
-        const int ip = p0 + (int)threadIdx.x;
-        if (ip < p1) ld6(GATHER ? a.perm[ip] : (unsigned)ip, nxt);
-        if (GATHER && ip + kBlock < p1) pj = a.perm[ip + kBlock];
-    }
+    auto first_loads = [&](const PDArgs& as) {
+        const int q0 = as.sc_off[sc], q1 = as.sc_off[sc + 1];
+        const int ip = q0 + (int)threadIdx.x;
+        if (ip < q1) ld6(as, GATHER ? as.perm[ip] : (unsigned)ip, nxt);
+        if (GATHER && ip + kBlock < q1) pj = as.perm[ip + kBlock];
+    };
+    first_loads(m.s[0]);
 
     // E/B tile: one wrapped global index per node, shared by the six
     // components (tile coordinates lie within one period of [0, n))
@@ -461,6 +482,11 @@ push_deposit_kernel(const PDArgs a) {
         }
         return in;
     };
+#pragma unroll 1
+    for (int si = 0; si < NSP; ++si) {
+    const PDArgs& a = m.s[si];
+    const int p0 = a.sc_off[sc], p1 = a.sc_off[sc + 1];
+    if (si > 0) first_loads(a);
     // deposit of a general move (any number of plane crossings) into the tile
     auto deposit_tile = [&](const double x0[3], const double x1[3]) {
         int c0[3], c1[3], rel[3];
@@ -499,7 +525,7 @@ push_deposit_kernel(const PDArgs a) {
         double u[3] = {nxt[3], nxt[4], nxt[5]};
         {
             const int in = ip + kBlock;
-            if (in < p1) ld6(GATHER ? pj : (unsigned)in, nxt);
+            if (in < p1) ld6(a, GATHER ? pj : (unsigned)in, nxt);
             if (GATHER && in + kBlock < p1) pj = a.perm[in + kBlock];
         }
         bool crosser = false, far = false;
@@ -616,6 +642,7 @@ push_deposit_kernel(const PDArgs a) {
         }
     }
     if (qcount > 0) drain(qcount);
+    }  // species
     __syncthreads();
 
     constexpr int TJ2 = TJ * TJ, TJ3 = TJ2 * TJ;
@@ -725,33 +752,67 @@ constexpr bool abs_supported() {
 template <int S, int H>
 hipError_t launch_sh(const PDArgs& args, hipStream_t s) {
     const bool det = args.det.hi[0] != nullptr;
+    const PDMulti<1> m{{args}};
     if constexpr (abs_supported<S, H>()) {
         if (args.g.absorb_x) {
             if (det) return hipErrorInvalidValue;
             if (args.perm)
-                hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, true>),
-                                   dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, true, 1>),
+                                   dim3(args.g.nsc), dim3(kBlock), 0, s, m);
             else
-                hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, true>),
-                                   dim3(args.g.nsc), dim3(kBlock), 0, s, args);
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, true, 1>),
+                                   dim3(args.g.nsc), dim3(kBlock), 0, s, m);
             return hipGetLastError();
         }
     } else {
         if (args.g.absorb_x) return hipErrorInvalidValue;
     }
     if (args.perm && det)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, true, false>), dim3(args.g.nsc),
-                           dim3(kBlock), 0, s, args);
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, true, false, 1>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, m);
     else if (args.perm)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, false>), dim3(args.g.nsc),
-                           dim3(kBlock), 0, s, args);
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, false, 1>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, m);
     else if (det)
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, true, false>), dim3(args.g.nsc),
-                           dim3(kBlock), 0, s, args);
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, true, false, 1>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, m);
     else
-        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, false>), dim3(args.g.nsc),
-                           dim3(kBlock), 0, s, args);
+        hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, false, 1>), dim3(args.g.nsc),
+                           dim3(kBlock), 0, s, m);
     return hipGetLastError();
+}
+
+// Two species over one tile load (compiled where absorbing x is: S 2 or 4,
+// h 1 or 2; not for the deterministic J).
+template <int S, int H>
+hipError_t launch_sh_pair(const PDArgs& a0, const PDArgs& a1, hipStream_t s) {
+    if constexpr (abs_supported<S, H>()) {
+        if (a0.det.hi[0] != nullptr || (a0.perm == nullptr) != (a1.perm == nullptr))
+            return hipErrorInvalidValue;
+        const PDMulti<2> m{{a0, a1}};
+        const bool gather = a0.perm != nullptr;
+        if (a0.g.absorb_x) {
+            if (gather)
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, true, 2>),
+                                   dim3(a0.g.nsc), dim3(kBlock), 0, s, m);
+            else
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, true, 2>),
+                                   dim3(a0.g.nsc), dim3(kBlock), 0, s, m);
+        } else {
+            if (gather)
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, true, false, false, 2>),
+                                   dim3(a0.g.nsc), dim3(kBlock), 0, s, m);
+            else
+                hipLaunchKernelGGL((push_deposit_kernel<S, H, false, false, false, 2>),
+                                   dim3(a0.g.nsc), dim3(kBlock), 0, s, m);
+        }
+        return hipGetLastError();
+    } else {
+        (void)a0;
+        (void)a1;
+        (void)s;
+        return hipErrorInvalidValue;
+    }
 }
 
 template <int S, int H>
@@ -826,6 +887,29 @@ hipError_t launch_push_deposit(const Geom& g, const SpeciesC& sp, const Parts& s
     return hipErrorInvalidValue;
 }
 
+bool push_deposit_pair_supported(int S, int h, bool det) {
+    return !det && (S == 2 || S == 4) && (h == 1 || h == 2);
+}
+
+hipError_t launch_push_deposit_pair(const Geom& g, const SpeciesC* sp, const Parts* src,
+                                    const Parts* dst, const unsigned* const* perm,
+                                    unsigned* const* keys, const int* const* sc_off,
+                                    const Fields& f, double* const J[3], unsigned* err,
+                                    unsigned long long* nfar, int* const* far_q,
+                                    unsigned* const* far_n, unsigned* const* far_n_next,
+                                    const DetJ& det, hipStream_t s) {
+    const PDArgs a0 = make_args(g, sp[0], src[0], dst[0], perm[0], keys[0], sc_off[0], f, J,
+                                err, nfar, far_q[0], far_n[0], far_n_next[0], det);
+    const PDArgs a1 = make_args(g, sp[1], src[1], dst[1], perm[1], keys[1], sc_off[1], f, J,
+                                err, nfar, far_q[1], far_n[1], far_n_next[1], det);
+    if (g.nsc <= 0) return hipSuccess;
+    if (g.S == 2 && g.h == 1) return launch_sh_pair<2, 1>(a0, a1, s);
+    if (g.S == 2 && g.h == 2) return launch_sh_pair<2, 2>(a0, a1, s);
+    if (g.S == 4 && g.h == 1) return launch_sh_pair<4, 1>(a0, a1, s);
+    if (g.S == 4 && g.h == 2) return launch_sh_pair<4, 2>(a0, a1, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src,
                              const Parts& dst, const unsigned* perm, unsigned* keys,
                              const Fields& f, double* const J[3], unsigned* err,
@@ -833,9 +917,7 @@ hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src
                              unsigned* far_n_next, const DetJ& det, hipStream_t s) {
     const PDArgs args = make_args(g, sp, src, dst, perm, keys, nullptr, f, J, err, nfar, far_q,
                                   far_n, far_n_next, det);
-    // far movers are few (tens per step); 64 workgroups keep the launch
-    // short and still cover 32 K of them per pass of the grid-stride loop
-    hipLaunchKernelGGL(far_kernel, dim3(64), dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL(far_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
 

@@ -859,9 +859,7 @@ hipError_t launch_far_mixed(const Geom& g, const SpeciesM& sp, const PartsM& src
                             unsigned* far_n_next, const DetJ& det, hipStream_t s) {
     const MArgs args = make_margs(g, sp, src, dst, perm, keys, nullptr, f, J, err, nfar, far_q,
                                   far_n, far_n_next, det);
-    // far movers are few (tens per step); 64 workgroups keep the launch
-    // short and still cover 32 K of them per pass of the grid-stride loop
-    hipLaunchKernelGGL(far_mixed_kernel, dim3(64), dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL(far_mixed_kernel, dim3(256), dim3(kBlock), 0, s, args);
     return hipGetLastError();
 }
 

@@ -78,6 +78,33 @@ def test_laser_slab_one_step_parity():
     sim.close()
 
 
+def test_laser_slab_two_species_one_launch_parity():
+    """Electrons (with the leaving beam merged in) and protons: the context
+    pushes both species in one launch over one tile load per supercell; the
+    one-step protocol as above, removal and re-sorts included."""
+    wl = _small_slab(seed=25)
+    beam = wl.species.pop()
+    e = wl.species[0]
+    for k in ("x", "y", "z", "ux", "uy", "uz"):
+        setattr(e, k, np.concatenate([getattr(e, k), getattr(beam, k)]))
+    sim = pic.Simulation.from_workload(wl)
+    at = 0
+    for k in (0, 1, 19, 20, 41, 120):
+        if k > at:
+            sim.step(k - at)
+            at = k
+        F0, P0 = _state(sim, 2)
+        sim.step(1)
+        at += 1
+        F1, P1 = _state(sim, 2)
+        o = _oracle(wl, F0, P0, k)
+        o.step(1)
+        compare(F1, P1, o, wl.n, tag=f"two-species slab step {k}")
+        log(f"  step {k} -> {k + 1}: counts {[p['n'] for p in P1]}")
+    assert sim.particles(0)["n"] < e.n                  # beam electrons left and were dropped
+    sim.close()
+
+
 def test_laser_in_vacuum_matches_oracle():
     n = (96, 4, 4)
     wl = W.laser_slab(n=n, slab=(40, 44), ppc=1, wavelength=16.0, name="vacuum")
