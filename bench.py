@@ -173,6 +173,53 @@ def laser_leg():
             "gauss_drift": d[4]}
 
 
+def precision_leg(steps=200):
+    """The precision variant at 128^3 x 32 particles per cell (67.1 M
+    particles): the FP32-mixed and the FP64 path side by side for ``steps``
+    steps from the same state (the mixed path's rounded positions and momenta,
+    read back from it and loaded into the FP64 context), each timed, with the
+    differences of field energy, kinetic energy and total momentum at the end."""
+    from paper_1608_01009_amd import pic
+    from paper_1608_01009_amd import workloads as W
+    import torch
+    wl = W.config4()
+    n = wl.nparticles
+    dev = torch.device("cuda:0")
+    log(f"precision variant: {wl.name}, {n} particles")
+    keys = ("x", "y", "z", "ux", "uy", "uz", "id")
+    out = {}
+    state = None
+    for prec in ("mixed", "fp64"):
+        sim = pic.Simulation.from_workload(wl, precision=prec)
+        if state is None:
+            state = {k: torch.empty(n, dtype=torch.int64 if k == "id" else torch.float64,
+                                    device=dev) for k in keys}
+            pic.pic_get_particles(sim.ctx, 0, capacity=n, out=state)
+        else:
+            sim.load_particles(0, *[state[k] for k in keys[:6]], state["id"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = sim.diagnostics()
+        u = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys[3:6]}
+        pic.pic_get_particles(sim.ctx, 0, capacity=n, out=u)
+        mom = [float(u[k].sum()) for k in keys[3:6]]
+        sim.close()
+        out[prec] = {"value": n * steps / wall, "ms_per_step": wall * 1e3 / steps, "W_E": d[0],
+                     "W_B": d[1], "K": d[2], "momentum": mom, "gauss_drift": d[4]}
+        log(f"precision variant {prec}: {wall*1e3/steps:.3f} ms/step, W_E {d[0]:.6e} "
+            f"K {d[2]:.6e} gauss drift {d[4]:.2e}")
+    a, b = out["fp64"], out["mixed"]
+    err = {"W_E_rel": abs(b["W_E"] - a["W_E"]) / abs(a["W_E"]),
+           "W_B_rel": abs(b["W_B"] - a["W_B"]) / max(abs(a["W_B"]), 1e-300),
+           "K_rel": abs(b["K"] - a["K"]) / abs(a["K"]),
+           "momentum_abs": [abs(x - y) for x, y in zip(b["momentum"], a["momentum"])]}
+    return {"workload": wl.name, "particles": n, "steps": steps, "fp64": a, "fp32_mixed": b,
+            "mixed_vs_fp64": err, "unit": "particle updates/s"}
+
+
 def adjoint_leg():
     """Gradient of the final field energy through 400 recorded steps of the
     32^3 / 16 ppc eight-mode workload (deterministic J, checkpoints every 20
@@ -217,6 +264,8 @@ def main():
                     help="skip the FP32-mixed leg (same workload, PIC_FP32_MIXED)")
     ap.add_argument("--no-laser", action="store_true",
                     help="skip the laser-plasma slab leg (1000 steps, 33.6 M particles)")
+    ap.add_argument("--no-precision-variant", action="store_true",
+                    help="skip the 128^3 x 32 FP32-mixed vs FP64 leg (67.1 M particles)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint leg (gradient through 400 recorded steps)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -304,6 +353,8 @@ def main():
         rec["fp32_mixed"] = mixed_leg(wl, args)
     if not args.no_laser:
         rec["laser_slab"] = laser_leg()
+    if not args.no_precision_variant:
+        rec["precision_variant"] = precision_leg()
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_leg()
     if args.copy_calibration_mib > 0:

@@ -112,20 +112,30 @@ __device__ unsigned block_exscan(unsigned v, unsigned* tmp) {
 }
 
 // Single workgroup: exclusive scan of up to kTile chunk sums, in place.
+// Exclusive scan of the m block sums in one workgroup, kTile at a time with
+// a running carry (m may exceed kTile for more than 2^24 histogram entries).
 __global__ void __launch_bounds__(kBlock) scan_sums_kernel(unsigned* sums, int m) {
     __shared__ unsigned tmp[kBlock];
-    unsigned local[kRounds];
-    unsigned s = 0;
-    for (int r = 0; r < kRounds; ++r) {
-        const int i = threadIdx.x * kRounds + r;
-        local[r] = (i < m) ? sums[i] : 0u;
-        s += local[r];
-    }
-    unsigned run = block_exscan(s, tmp);
-    for (int r = 0; r < kRounds; ++r) {
-        const int i = threadIdx.x * kRounds + r;
-        if (i < m) sums[i] = run;
-        run += local[r];
+    __shared__ unsigned carry_s;
+    unsigned carry = 0;
+    for (int c0 = 0; c0 < m; c0 += kTile) {
+        unsigned local[kRounds];
+        unsigned s = 0;
+        for (int r = 0; r < kRounds; ++r) {
+            const int i = c0 + threadIdx.x * kRounds + r;
+            local[r] = (i < m) ? sums[i] : 0u;
+            s += local[r];
+        }
+        unsigned run = block_exscan(s, tmp) + carry;
+        for (int r = 0; r < kRounds; ++r) {
+            const int i = c0 + threadIdx.x * kRounds + r;
+            if (i < m) sums[i] = run;
+            run += local[r];
+        }
+        if (threadIdx.x == kBlock - 1) carry_s = run;
+        __syncthreads();
+        carry = carry_s;
+        __syncthreads();
     }
 }
 
@@ -435,9 +445,6 @@ hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const P
         return hipGetLastError();
     }
     Scratch sc = carve(scratch, n);
-    const int nb = nblk(n, kTile);
-    const int nsum = nblk((int64_t)(1 << kMaxBits) * nb, kTile);
-    if (nsum > kTile) return hipErrorInvalidValue;  // more than 2^24 histogram entries
     if (!keys) {
         hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, g, n, src.x, src.y,
                            src.z, src.ux, src.uy, src.uz, sc.k0, err);

@@ -228,3 +228,47 @@ def test_mixed_long_run_against_fp64_gpu():
     assert b["gauss"] <= 1e-4
     for key in ("WE", "K"):
         assert abs(a[key] - b[key]) <= 1e-2 * abs(a[key]), key
+
+
+def test_precision_variant_full_size_128c_32ppc():
+    """The 128^3 x 32 ppc recipe (67,108,864 particles) in both precisions for
+    200 steps from the same state (the mixed path's rounded state loaded into
+    the FP64 context): charge, Gauss drift and the ensemble energies as in the
+    16^3 run above, at the full size."""
+    import torch
+    wl = W.config4()
+    n = wl.nparticles
+    log(f"  precision variant at full size: {n} particles")
+    dev = torch.device("cuda:0")
+    keys = ("x", "y", "z", "ux", "uy", "uz", "id")
+    out = {}
+    state = None
+    for prec in ("mixed", "fp64"):
+        sim = pic.Simulation.from_workload(wl, precision=prec)
+        try:
+            if state is None:
+                state = {k: torch.empty(n, dtype=torch.int64 if k == "id" else torch.float64,
+                                        device=dev) for k in keys}
+                pic.pic_get_particles(sim.ctx, 0, capacity=n, out=state)
+                # the load's re-sort (a histogram scan over more than 2^24
+                # entries) grouped the 67 M particles by supercell
+                c = [torch.floor(state[k]).to(torch.int64) // wl.S for k in ("x", "y", "z")]
+                ns = [v // wl.S for v in wl.n]
+                sc = c[0] + ns[0] * (c[1] + ns[1] * c[2])
+                assert bool(torch.all(sc[1:] >= sc[:-1]))
+                assert int(torch.unique(state["id"]).numel()) == n
+            else:
+                sim.load_particles(0, *[state[k] for k in keys[:6]], state["id"])
+            sim.step(200)
+            d = sim.diagnostics()
+            out[prec] = dict(WE=d[0], WB=d[1], K=d[2], Q=d[3], gauss=d[4])
+        finally:
+            sim.close()
+    a, b = out["fp64"], out["mixed"]
+    log(f"  200 steps, FP64: {a}")
+    log(f"  200 steps, mixed: {b}")
+    assert a["Q"] == b["Q"]
+    assert a["gauss"] <= 1e-11
+    assert b["gauss"] <= 1e-4
+    for key in ("WE", "K"):
+        assert abs(a[key] - b[key]) <= 1e-2 * abs(a[key]), key
