@@ -394,6 +394,36 @@ push_deposit_kernel(const PDMulti<NSP> m) {
     __shared__ double qb[kWaves][6][QCAP];
 
     const int sc = xcd_block(blockIdx.x, gridDim.x);
+    const Geom& g = a.g;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int sx = sc % g.ns[0];
+    const int syz = sc / g.ns[0];
+    const int sy = syz % g.ns[1], sz = syz / g.ns[1];
+    const int base[3] = {sx * S, sy * S, sz * S};          // first cell of the supercell
+    const int org[3] = {base[0] - H - 1, base[1] - H - 1, base[2] - H - 1};  // tile origin
+    const bool near = nx >= H + 2 && ny >= H + 2 && nz >= H + 2;
+    // E/B tile values of this thread's nodes: one wrapped global index per
+    // node, shared by the six components (tile coordinates lie within one
+    // period of [0, n)).  SPEC: one species on periodic boundaries, where
+    // supercells are rarely empty: the tile loads go out before the particle
+    // ranges arrive, so that the two latencies overlap.
+    constexpr bool SPEC = NSP == 1 && !ABS;
+    constexpr int TN = (T3 + kBlock - 1) / kBlock;
+    double tv[TN][6];
+    auto tile_loads = [&]() {
+#pragma unroll
+        for (int i = 0; i < TN; ++i) {
+            const int r = (int)threadIdx.x + i * kBlock;
+            if (r < T3) {
+                const int tz = r / T2, ty = (r / T) % T, tx = r % T;
+                const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
+                const bool outside = ABS && (org[0] + tx < 0 || org[0] + tx >= nx);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) tv[i][c] = outside ? 0.0 : a.EB[c][gi];
+            }
+        }
+    };
+    if (SPEC) tile_loads();
     {
         // empty supercell: uniform exit before any barrier
         bool any = false, over = false;
@@ -410,14 +440,6 @@ push_deposit_kernel(const PDMulti<NSP> m) {
         }
     }
 
-    const Geom& g = a.g;
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int sx = sc % g.ns[0];
-    const int syz = sc / g.ns[0];
-    const int sy = syz % g.ns[1], sz = syz / g.ns[1];
-    const int base[3] = {sx * S, sy * S, sz * S};          // first cell of the supercell
-    const int org[3] = {base[0] - H - 1, base[1] - H - 1, base[2] - H - 1};  // tile origin
-    const bool near = nx >= H + 2 && ny >= H + 2 && nz >= H + 2;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -446,20 +468,27 @@ push_deposit_kernel(const PDMulti<NSP> m) {
     auto first_loads = [&](const PDArgs& as) {
         const int q0 = as.sc_off[sc], q1 = as.sc_off[sc + 1];
         const int ip = q0 + (int)threadIdx.x;
-        if (ip < q1) ld6(as, GATHER ? as.perm[ip] : (unsigned)ip, nxt);
-        if (GATHER && ip + kBlock < q1) pj = as.perm[ip + kBlock];
+        if (GATHER) {
+            if (ip < q1) ld6(as, as.perm[ip], nxt);
+            if (ip + kBlock < q1) pj = as.perm[ip + kBlock];
+        } else {
+            // every lane loads (past the end: the spare slot), so that the
+            // count of loads in flight is known where the tile values are
+            // consumed, and that wait leaves these loads in flight
+            ld6(as, ip < q1 ? (unsigned)ip : as.src.spare, nxt);
+        }
     };
     first_loads(m.s[0]);
-
-    // E/B tile: one wrapped global index per node, shared by the six
-    // components (tile coordinates lie within one period of [0, n))
-    for (int r = threadIdx.x; r < T3; r += kBlock) {
-        const int tz = r / T2, ty = (r / T) % T, tx = r % T;
-        const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
-        const int li = tx + EL::PY * ty + EL::PZ * tz;
-        const bool outside = ABS && (org[0] + tx < 0 || org[0] + tx >= nx);
+    if (!SPEC) tile_loads();
 #pragma unroll
-        for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = outside ? 0.0 : a.EB[c][gi];
+    for (int i = 0; i < TN; ++i) {
+        const int r = (int)threadIdx.x + i * kBlock;
+        if (r < T3) {
+            const int tz = r / T2, ty = (r / T) % T, tx = r % T;
+            const int li = tx + EL::PY * ty + EL::PZ * tz;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = tv[i][c];
+        }
     }
     for (int t = threadIdx.x; t < JT_BYTES / 4; t += kBlock) ((int*)jraw)[t] = 0;
     __syncthreads();
