@@ -12,14 +12,17 @@
 //   particles:         the vector-Jacobian product of gather -> Boris ->
 //                      advance -> deposit, one particle per thread, with the
 //                      deposit's gradient read from lJ and the transposed
-//                      interpolation scattered into lE / lB with FP64 atomics;
+//                      interpolation summed per workgroup in an LDS tile
+//                      (its particles are consecutive in the supercell-sorted
+//                      order, so their stencils share a small box) and added
+//                      into lE / lB with one FP64 atomic per node;
 //   re-sort:           the adjoint of a particle moves back to the particle's
 //                      slot before the re-sort.
 //
 // The kernels read the forward state of the step (positions, momenta and the
-// fields at its start), which the host recomputes from checkpoints.  They use
-// global memory directly: the adjoint runs once per gradient, not in the
-// stepping loop, so none of the forward kernels' LDS tiling is repeated here.
+// fields at its start), which the host recomputes from checkpoints.  Apart
+// from the transposed interpolation they use global memory directly: the
+// adjoint runs once per gradient, not in the stepping loop.
 #include "pic_device.h"
 #include "pic_internal.h"
 
@@ -27,6 +30,8 @@ namespace pic {
 namespace {
 
 constexpr int kAdjBlock = 256;
+// Edge (nodes) of the LDS tile of the transposed interpolation.
+constexpr int kAdjTile = 10;
 
 int grid_for(int64_t n) {
     int64_t b = (n + kAdjBlock - 1) / kAdjBlock;
@@ -112,8 +117,8 @@ struct Cic {
     double v[8];   // v[a + 2 b + 4 e] = F[i + (a, b, e)]
 };
 
-__device__ __forceinline__ void cic_load(const Geom& g, const double* F, int c, const double x[3],
-                                         Cic& p) {
+// Stencil position of component c at x: lower node and fractions.
+__device__ __forceinline__ void cic_place(int c, const double x[3], Cic& p) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -122,6 +127,11 @@ __device__ __forceinline__ void cic_load(const Geom& g, const double* F, int c, 
         p.i[d] = (int)fl;
         p.f[d] = xi - fl;
     }
+}
+
+__device__ __forceinline__ void cic_load(const Geom& g, const double* F, int c, const double x[3],
+                                         Cic& p) {
+    cic_place(c, x, p);
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -162,6 +172,22 @@ __device__ __forceinline__ void cic_scatter(const Geom& g, double* F, const Cic&
 #pragma unroll
             for (int a = 0; a < 2; ++a)
                 atomicAdd(F + lin3(g, p.i[0] + a, p.i[1] + b, p.i[2] + e),
+                          lF * wgt(a, p.f[0]) * wgt(b, p.f[1]) * wgt(e, p.f[2]));
+}
+
+// The same into an LDS tile of edge kAdjTile whose node (0, 0, 0) is the
+// unwrapped lattice node lo (every node of the stencil lies in the tile).
+__device__ __forceinline__ void cic_scatter_tile(double* T, const int lo[3], const Cic& p,
+                                                 double lF) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                atomicAdd(T + (p.i[0] + a - lo[0]) +
+                              kAdjTile * ((p.i[1] + b - lo[1]) + kAdjTile * (p.i[2] + e - lo[2])),
                           lF * wgt(a, p.f[0]) * wgt(b, p.f[1]) * wgt(e, p.f[2]));
 }
 
@@ -251,7 +277,8 @@ __device__ __forceinline__ void vb_move_grad(const Geom& g, const double* const 
     double A[3] = {x0[0], x0[1], x0[2]};
     int cell[3] = {c0[0], c0[1], c0[2]};
     double gPrev[3] = {0.0, 0.0, 0.0};   // gradient at the current segment's start point
-#pragma unroll
+    // one segment at a time: its twelve lJ loads are the only ones in flight
+#pragma unroll 1
     for (int k = 0; k < 4; ++k) {
         if (k > left) break;
         const int kk = k < 3 ? k : 2;      // crossing k exists only for k < left <= 3
@@ -311,16 +338,51 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 __global__ void __launch_bounds__(kAdjBlock) particle_adjoint_kernel(AdjArgs A) {
 #pragma clang fp contract(off)
     const Geom& g = A.g;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < A.n; p += gridDim.x * blockDim.x) {
-        const double x0[3] = {A.x[0][p], A.x[1][p], A.x[2][p]};
-        const double u0[3] = {A.u[0][p], A.u[1][p], A.u[2][p]};
-        // forward values
-        Cic cp[6];
+    // The particles of a workgroup are consecutive in the stored order, which
+    // is sorted by supercell: their interpolation nodes usually lie in a small
+    // box.  Then the transposed interpolation is summed in an LDS tile over
+    // that box and added into lE / lB once per node; otherwise (a box wider
+    // than the tile, e.g. across the periodic boundary) each particle adds
+    // into global memory directly.
+    constexpr int TB = kAdjTile, TB3 = TB * TB * TB;
+    __shared__ double ltile[6][TB3];
+    __shared__ int box[6];
+    for (int p0 = blockIdx.x * kAdjBlock; p0 < A.n; p0 += gridDim.x * kAdjBlock) {
+        const int p = p0 + (int)threadIdx.x;
+        const bool valid = p < A.n;
+        if (threadIdx.x < 3) box[threadIdx.x] = 0x7fffffff;
+        else if (threadIdx.x < 6) box[threadIdx.x] = -0x7fffffff;
+        __syncthreads();
+        double x0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                x0[d] = A.x[d][p];
+                u0[d] = A.u[d][p];
+            }
+            // nodes of every stagger: floor(x) - 1 .. floor(x) + 1
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int c = (int)floor(x0[d]);
+                atomicMin(&box[d], c - 1);
+                atomicMax(&box[3 + d], c + 1);
+            }
+        }
+        __syncthreads();
+        const int lo[3] = {box[0], box[1], box[2]};
+        const bool tiled = box[3] - lo[0] < TB && box[4] - lo[1] < TB && box[5] - lo[2] < TB;
+        if (tiled)
+            for (int t = threadIdx.x; t < 6 * TB3; t += kAdjBlock) (&ltile[0][0])[t] = 0.0;
+        __syncthreads();
+        if (valid) {
+        // forward values (the stencils are recomputed for the scatter below,
+        // so that only the values and their gradients stay live)
         double F[6], dF[6][3];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            cic_load(g, A.EB[c], c, x0, cp[c]);
-            F[c] = cic_value_grad(cp[c], dF[c]);
+            Cic cp;
+            cic_load(g, A.EB[c], c, x0, cp);
+            F[c] = cic_value_grad(cp, dF[c]);
         }
         const double* E = F;
         const double* Bf = F + 3;
@@ -394,13 +456,32 @@ __global__ void __launch_bounds__(kAdjBlock) particle_adjoint_kernel(AdjArgs A) 
         for (int c = 0; c < 6; ++c) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) lx0[d] += lF[c] * dF[c][d];
-            cic_scatter(g, A.lEB[c], cp[c], lF[c]);
+            Cic cp;
+            cic_place(c, x0, cp);
+            if (tiled)
+                cic_scatter_tile(ltile[c], lo, cp, lF[c]);
+            else
+                cic_scatter(g, A.lEB[c], cp, lF[c]);
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             A.lx[d][p] = lx0[d];
             A.lu[d][p] = lum[d];
         }
+        }  // valid
+        __syncthreads();
+        if (tiled) {
+            for (int t = threadIdx.x; t < TB3; t += kAdjBlock) {
+                const int tx = t % TB, ty = (t / TB) % TB, tz = t / (TB * TB);
+                const int gi = lin3(g, lo[0] + tx, lo[1] + ty, lo[2] + tz);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double v = ltile[c][t];
+                    if (v != 0.0) atomicAdd(A.lEB[c] + gi, v);
+                }
+            }
+        }
+        __syncthreads();   // the tile and the box are reused by the next range
     }
 }
 
