@@ -8,6 +8,9 @@ removal, laser current sheet) against the oracle.
   the start, around a re-sort that drops removed particles, and while the
   laser pulse crosses the slab; removed particles (x = -1) and the stored
   order agree bit for bit;
+* the full-size slab (256 x 128 x 128 cells, 33.6 M particles, the launch
+  configuration the benchmark times): one step late in the run, with the pulse
+  inside the plasma and ending with a re-sort, against the oracle's step;
 * the laser in vacuum: fields after 300 steps against the oracle's;
 * the diagnostics (Gauss residual at the inside nodes, charge of the
   particles inside) and the error codes of the boundary and source settings.
@@ -168,3 +171,33 @@ def test_diagnostics_and_error_codes():
         per.set_laser(0.1, 0.3, 10.0, 3)
     assert e.value.code == pic.PIC_EINVAL
     per.close()
+
+
+@pytest.mark.timeout(400)
+def test_laser_slab_full_size_one_step():
+    """The laser-plasma slab at its full size (256 x 128 x 128 cells, 33,554,432
+    particles, both species in one launch, re-sorted every 10 steps) in the
+    configuration the benchmark times: 509 steps on the GPU (the pulse has
+    entered the plasma: electrons at up to 0.8 c, cell crossers and far movers),
+    then step 509 -> 510, which ends with a re-sort, against the oracle's step
+    from the same state: every particle (stored order bit for bit, cells bit
+    for bit, positions within 2 ulp, momenta 1e-12), J, E and B."""
+    wl = W.config3()
+    k = 509
+    sim = pic.Simulation.from_workload(wl)
+    log(f"  full-size slab: {wl.nparticles} particles, {k} steps on the GPU")
+    sim.step(k)
+    F0, P0 = _state(sim, 2)
+    sim.step(1)
+    F1, P1 = _state(sim, 2)
+    log(f"  global-path pushes so far: {int(sim.counters()[0])}")
+    sim.close()
+    u = P0[0]["uy"][:P0[0]["n"]]
+    log(f"  electrons max |u_y| {np.max(np.abs(u)):.2f}")
+    assert np.max(np.abs(u)) > 0.3
+    o = _oracle(wl, F0, P0, k)
+    del F0, P0
+    log("  oracle step at full size")
+    o.step(1)
+    rep = compare(F1, P1, o, wl.n, tag=f"full-size slab step {k}")
+    log(f"  {rep}")
