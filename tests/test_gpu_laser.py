@@ -84,12 +84,19 @@ def test_laser_slab_one_step_parity():
 def test_laser_slab_two_species_one_launch_parity():
     """Electrons (with the leaving beam merged in) and protons: the context
     pushes both species in one launch over one tile load per supercell; the
-    one-step protocol as above, removal and re-sorts included."""
+    one-step protocol as above, removal and re-sorts included.  A cluster of
+    slow electrons in the supercells at x = 12..16, next to empty ones at
+    x = 8..12 and without protons, gives supercells where one species is
+    absent."""
     wl = _small_slab(seed=25)
     beam = wl.species.pop()
+    rng = np.random.default_rng(26)
+    nc = 40
+    cluster = W.Species(-1.0, 1.0, 0.01, rng.uniform(12.5, 15.5, nc), rng.uniform(0, 8, nc),
+                        rng.uniform(0, 8, nc), *[rng.normal(scale=0.05, size=nc) for _ in range(3)])
     e = wl.species[0]
     for k in ("x", "y", "z", "ux", "uy", "uz"):
-        setattr(e, k, np.concatenate([getattr(e, k), getattr(beam, k)]))
+        setattr(e, k, np.concatenate([getattr(e, k), getattr(beam, k), getattr(cluster, k)]))
     sim = pic.Simulation.from_workload(wl)
     at = 0
     for k in (0, 1, 19, 20, 41, 120):
