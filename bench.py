@@ -52,6 +52,19 @@ def algorithmic_bytes_per_launch(nparticles: int, ncell: int, precision: str = "
     return nparticles * per_particle + ncell * 72
 
 
+# The paper's own figures for the same step in FP64 (context only: other
+# hardware and a 40^3 x 50 ppc, 1000-step workload).  Updates/s are 3.2e9
+# particle updates over the overall times of its Table 6 (optimised code);
+# the GFLOPS are the ones it states for the optimised code.
+PAPER_CONTEXT = {
+    "source": "arXiv:1608.01009, Table 6 and its performance discussion",
+    "workload": "40^3 cells x 50 particles per cell, 1000 steps, FP64",
+    "xeon_phi_7250_knl_68c": {"particle_updates_per_s": 3.2e9 / 10.75, "gflops_fp64": 100.0},
+    "xeon_e5_2697v3_haswell_14c": {"particle_updates_per_s": 3.2e9 / 25.27, "gflops_fp64": 42.5},
+    "xeon_phi_7120_knc_61c": {"particle_updates_per_s": 3.2e9 / 37.32},
+}
+
+
 def measured_traffic(counters=COUNTERS, kernel_src=KERNEL_SRC):
     """HBM bytes per push+deposit launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
@@ -348,6 +361,7 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch,
                      "avg_launch_us": push_ms_avg * 1e3},
         "cpu_baseline": None,
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_mixed:
         rec["fp32_mixed"] = mixed_leg(wl, args)
