@@ -55,6 +55,8 @@ def _create(**kw):
     (dict(species=[(-1.0, 0.0, 0.1, 10)]), "mass"),
     (dict(species=[(-1.0, 1.0, -0.1, 10)]), "weight"),
     (dict(species=[(-1.0, 1.0, 0.1, -1)]), "capacity"),
+    (dict(species=[(-1.0, 1.0, 0.1, 1 << 29)]), "capacity"),     # 32-bit byte offsets
+    (dict(n=(2048, 1024, 1024), dt=0.25), "grid too large"),
     (dict(species=[(1e-280, 1.0, 0.1, 10)]), "charge dt"),
     (dict(precision=2), "precision"),
     (dict(precision="mixed", n=(2048, 8, 8)), "1024 cells"),
