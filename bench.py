@@ -85,6 +85,29 @@ def measured_traffic(counters=COUNTERS, kernel_src=KERNEL_SRC):
         return None
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 10):
+    """Device-to-device copy bandwidth (bytes read + written per second) of a
+    plain FP64 tensor copy, timed with HIP events on torch's stream: the
+    practical ceiling next to the 8 TB/s specification."""
+    import torch
+    nel = mib * (1 << 20) // 8
+    a = torch.ones(nel, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    t1.synchronize()
+    us = t0.elapsed_time(t1) * 1e3 / reps
+    del a, b
+    gbs = 2.0 * nel * 8 / (us * 1e-6) / 1e9
+    log(f"copy bandwidth: {gbs:.0f} GB/s ({mib} MiB read and written, {us:.1f} us)")
+    return {"GBs": gbs, "bytes_per_copy": 2 * nel * 8, "us_per_copy": us,
+            "method": f"torch copy_ of a {mib} MiB FP64 tensor, HIP events, {reps} repeats"}
+
+
 def cpu_baseline(wl, steps: int):
     """The oracle as it stands (single-threaded C, FP64) on the host: `steps`
     full steps of the same workload."""
@@ -371,6 +394,8 @@ def main():
         rec["precision_variant"] = precision_leg()
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_leg()
+    rec["hbm_copy"] = copy_bandwidth()
+    rec["roofline"]["frac_of_copy"] = achieved / rec["hbm_copy"]["GBs"]
     if args.copy_calibration_mib > 0:
         nel = args.copy_calibration_mib * (1 << 20) // 8
         a = torch.ones(nel, dtype=torch.float64, device="cuda")
