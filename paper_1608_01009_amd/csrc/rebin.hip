@@ -252,28 +252,29 @@ __global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
     const int sc = blockIdx.x;
     const int s0 = sc_off[sc], s1 = sc_off[sc + 1];
     if (s0 >= s1) return;
-    for (int l = threadIdx.x; l < S3; l += kBlock) cnt[l] = 0;
-    __syncthreads();
     const unsigned kb = (unsigned)sc * (unsigned)S3;
-    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) atomicAdd(&cnt[key[i] - kb], 1);
+    // cell starts straight from the sorted keys: the particle where the cell
+    // changes starts every cell from the previous particle's cell + 1 to its
+    // own (no atomics: consecutive lanes mostly share a cell); the cells after
+    // the last particle start at s1
+    for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
+        const int loc = (int)(key[i] - kb);
+        const int prev = (i == s0) ? -1 : (int)(key[i - 1] - kb);
+        for (int l = prev + 1; l <= loc; ++l) cst[l] = i;
+        if (i == s1 - 1)
+            for (int l = loc + 1; l < S3; ++l) cst[l] = s1;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < S3; l += kBlock) cnt[l] = (l + 1 < S3 ? cst[l + 1] : s1) - cst[l];
     __syncthreads();
     const int nwords = (S3 + 63) / 64;
     if (threadIdx.x < 64) {
-        // wave 0: cell starts (exclusive prefix of the counts) and the
-        // largest count, 64 cells at a time
+        // wave 0: the largest count, 64 cells at a time
         const int lane = threadIdx.x;
-        int carry = s0, mx = 0;
+        int mx = 0;
         for (int w = 0; w < nwords; ++w) {
             const int l = 64 * w + lane;
             const int c = l < S3 ? cnt[l] : 0;
-            int incl = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int t = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += t;
-            }
-            if (l < S3) cst[l] = carry + incl - c;
-            carry += __shfl(incl, 63, 64);
             mx = c > mx ? c : mx;
         }
 #pragma unroll
