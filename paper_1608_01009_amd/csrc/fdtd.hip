@@ -31,7 +31,7 @@ struct FArgs {
 };
 
 constexpr int YB = 8;                 // block edge in cells
-constexpr int YT = 512;               // threads per workgroup
+constexpr int YT = 256;               // threads per workgroup
 constexpr int NE = YB + 3;            // E tile edge: cells lo-1 .. hi+1
 constexpr int NBt = YB + 2;           // B tile edge: cells lo-1 .. hi
 constexpr int NE1 = YB + 1;           // E' tile edge: cells lo .. hi
