@@ -445,8 +445,9 @@ push_deposit_kernel(const PDMulti<NSP> m) {
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // software pipeline: the next particle's state is loaded one iteration
-    // ahead; the first particle's loads are issued before the tile loads so
-    // that the two latencies overlap
+    // ahead; the first particle's loads and the tile loads are in flight
+    // together (with more than one species, or absorbing x, the particle
+    // loads go first; otherwise the tile loads, see SPEC above)
     double nxt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     // Particle arrays are addressed with 32-bit byte offsets from the scalar
     // base of each array (arrays are below 4 GiB: capacity < 2^29), so the
