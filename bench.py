@@ -52,6 +52,26 @@ def algorithmic_bytes_per_launch(nparticles: int, ncell: int, precision: str = "
     return nparticles * per_particle + ncell * 72
 
 
+def algorithmic_bytes_per_update(ppc: float, rebin_every: int, precision: str = "fp64") -> float:
+    """What one particle update of the whole step must move: the particle
+    state read and written once (2 s_p, s_p = 48 B in FP64, 28 B mixed); the
+    grid's 24 FP64 array passes per step (6 E/B reads for the gather, 3 J
+    writes, 9 reads and 6 writes in the fused Yee update) shared by the ppc
+    particles of a cell; and the re-sort moving the state twice plus about
+    32 B of keys and ranks every rebin_every steps."""
+    sp = 48 if precision == "fp64" else 28
+    return 2 * sp + 24 * 8 / ppc + (2 * sp + 32) / rebin_every
+
+
+def step_roofline(updates_per_s: float, ppc: float, rebin_every: int, precision: str = "fp64"):
+    """The whole step (every kernel, launch gaps included) against the HBM
+    peak: updates/s x algorithmic bytes per update."""
+    b = algorithmic_bytes_per_update(ppc, rebin_every, precision)
+    achieved = updates_per_s * b / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_update": b}
+
+
 # The paper's own figures for the same step in FP64 (context only: other
 # hardware and a 40^3 x 50 ppc, 1000-step workload).  Updates/s are 3.2e9
 # particle updates over the overall times of its Table 6 (optimised code);
@@ -151,6 +171,7 @@ def mixed_leg(wl, args):
         f"{push_ms_avg*1e3:.1f} us/launch; gauss drift {d[4]:.3e}")
     return {"value": n * args.steps / wall, "unit": "particle updates/s",
             "ms_per_step": wall * 1e3 / args.steps, "dtype": "f32 (FP64 fields and J)",
+            "step_roofline": step_roofline(n * args.steps / wall, 50, wl.R, "mixed"),
             "roofline": {"bound": "hbm", "kernel": "push_mixed_kernel<4, 1, false, false>",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
@@ -309,9 +330,8 @@ def main():
                          "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the PIC step here is built and timed on a "
-              "single MI355X (multi-GPU domain decomposition is not part of this build).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the PIC step is timed on a single MI355X "
+              "(multi-GPU domain decomposition is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     from paper_1608_01009_amd import pic
@@ -383,6 +403,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch,
                      "avg_launch_us": push_ms_avg * 1e3},
+        "step_roofline": step_roofline(value, 50, wl.R),
         "cpu_baseline": None,
         "paper_context": PAPER_CONTEXT,
     }
