@@ -160,6 +160,40 @@ def test_timers_and_counters():
     sim.close()
 
 
+def test_long_run_invariants_64cubed_50ppc():
+    """The benchmark's workload (13,107,200 particles) through its 200 steps and
+    ten re-sorts: after every re-sort period the Gauss residual and div B are
+    unchanged to rounding (the deposition conserves charge exactly), the total
+    charge is exact, and at the end the field and kinetic energies the library
+    reports equal the oracle's evaluation of the GPU's state."""
+    wl = W.config2()
+    sp = wl.species[0]
+    sim = pic.Simulation.from_workload(wl)
+    o = oracle_for(wl)
+    o.load_particles(0, *sp.arrays())
+    o.set_fields(wl.fields)
+    rho_scale = np.max(np.abs(o.rho()))
+    q = sp.charge * sp.weight * sp.n
+    for block in range(10):
+        sim.step(wl.R)
+        d = sim.diagnostics()
+        assert d[4] <= 1e-12 * rho_scale                  # Gauss residual unchanged
+        assert d[5] <= 1e-13                              # div B unchanged
+        assert d[3] == pytest.approx(q, rel=1e-12)        # total charge
+        assert d[7] == wl.R * (block + 1)
+    log(f"  64^3 x 50 after {int(d[7])} steps: gauss drift {d[4]:.2e} (rho scale "
+        f"{rho_scale:.2e}), div B drift {d[5]:.2e}, W_E {d[0]:.6e} W_B {d[1]:.6e} K {d[2]:.6e}")
+    assert sim.counters()[1] == 10                       # re-sorts
+    F, P = read_state(sim, 1)
+    sim.close()
+    o.set_state([[P[0][k][:P[0]["n"]] for k in KEYS]], F[:6], 0)
+    del F, P
+    WE, WB = o.field_energy()
+    assert d[0] == pytest.approx(WE, rel=1e-12)
+    assert d[1] == pytest.approx(WB, rel=1e-12)
+    assert d[2] == pytest.approx(o.kinetic(), rel=1e-10)
+
+
 def test_full_size_64cubed_50ppc_one_step():
     """The benchmark's workload at its full size (13,107,200 particles, S = 4,
     h = 1): one step from the loaded state, checked against the oracle's
