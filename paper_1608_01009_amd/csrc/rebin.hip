@@ -224,9 +224,12 @@ __global__ void __launch_bounds__(kBlock) scatter_kernel(const unsigned* key_in,
 // sc_off[s] = first sorted index whose supercell is >= s; sc_off[nsc] = n.
 __global__ void __launch_bounds__(kBlock) offsets_kernel(const unsigned* key, int n, int S3,
                                                          int nsc, int* sc_off) {
+    // supercell of a key: a shift when S^3 is a power of two (S = 1, 2, 4)
+    const int sh = (S3 & (S3 - 1)) == 0 ? __builtin_ctz((unsigned)S3) : -1;
+    auto sc_of = [&](unsigned k) { return (int)(sh >= 0 ? k >> sh : k / (unsigned)S3); };
     for (int i = blockIdx.x * kBlock + threadIdx.x; i <= n; i += gridDim.x * kBlock) {
-        const int prev = (i == 0) ? -1 : (int)(key[i - 1] / (unsigned)S3);
-        const int cur = (i == n) ? nsc : (int)(key[i] / (unsigned)S3);
+        const int prev = (i == 0) ? -1 : sc_of(key[i - 1]);
+        const int cur = (i == n) ? nsc : sc_of(key[i]);
         for (int s = prev + 1; s <= cur; ++s) sc_off[s] = i;
     }
 }
@@ -240,10 +243,10 @@ constexpr int kMaxS3 = 256;
 constexpr int kMaskWords = kMaxS3 / 64;
 constexpr int kMaxRounds = 512;
 
-__global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
-                                                            const unsigned* perm_sorted,
-                                                            const int* sc_off, int S3,
-                                                            unsigned* out) {
+__global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* __restrict__ key,
+                                                            const unsigned* __restrict__ perm_sorted,
+                                                            const int* __restrict__ sc_off, int S3,
+                                                            unsigned* __restrict__ out) {
     __shared__ int cnt[kMaxS3];
     __shared__ int cst[kMaxS3];
     __shared__ int rstart[kMaxRounds + 1];
@@ -302,6 +305,9 @@ __global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* key,
     __syncthreads();
     const int maxc = maxc_s;
     if (maxc <= kMaxRounds) {
+        // independent iterations (out does not alias the inputs): unrolled so
+        // that several key loads are in flight per lane
+#pragma unroll 4
         for (int i = s0 + threadIdx.x; i < s1; i += kBlock) {
             const int loc = (int)(key[i] - kb);
             const int rank = i - cst[loc];
