@@ -54,6 +54,15 @@ __device__ __forceinline__ double ddx(double v, double dx) {
     return UNIT ? v : v / dx;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Give each XCD a contiguous range of blocks (with x fastest, whole
+// layers of blocks along z), so that the halos of neighbouring blocks in x and
+// y are fetched from HBM once per XCD rather than once per block.
+__device__ __forceinline__ int yee_xcd_block(int b, int nb) {
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 template <bool UNIT>
 __global__ void __launch_bounds__(YT) yee_kernel(const FArgs a) {
 #pragma clang fp contract(off)
@@ -61,7 +70,7 @@ __global__ void __launch_bounds__(YT) yee_kernel(const FArgs a) {
     __shared__ double bt[3][NBt * NBt * NBt];
     __shared__ double e1[3][NE1 * NE1 * NE1];
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    const int b = blockIdx.x;
+    const int b = yee_xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int bxi = b % a.nb[0], byz = b / a.nb[0];
     const int byi = byz % a.nb[1], bzi = byz / a.nb[1];
     const int lo[3] = {bxi * YB, byi * YB, bzi * YB};
