@@ -345,9 +345,20 @@ __global__ void __launch_bounds__(kBlock) permute_kernel(int n, const unsigned* 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n, const unsigned* perm,
-                                                             const int64_t* src, int64_t* dst) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Give each XCD a contiguous range of blocks: the gathered reads of one
+// supercell's particles (old slots close to each other) then share one L2.
+__device__ __forceinline__ int xcd_range_block(int b, int nb) {
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+__global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n,
+                                                             const unsigned* __restrict__ perm,
+                                                             const int64_t* __restrict__ src,
+                                                             int64_t* __restrict__ dst) {
+    const int b = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
+    for (int i = b * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         dst[i] = src[perm[i]];
 }
 
