@@ -412,11 +412,10 @@ void orc_add_laser(const orc_grid* g, double* Jy, int64_t plane, double E0, doub
  * Per-cell particle storage grouped by supercells (Sections 3 and 4.3).
  *
  * The key orders particles by supercell (x-fastest over supercells), then by
- * cell inside the supercell (x-fastest).  A stable sort on that key groups
- * every cell's particles, in their previous order.  Inside each supercell the
- * cells' lists are then stored interleaved in rounds: round r holds, in
- * increasing cell order, the r-th particle of every cell of the supercell
- * that has more than r particles.
+ * cell inside the supercell (x-fastest).  A stable sort on that key stores
+ * every cell's particles together, in their previous order, and the cells of
+ * a supercell next to each other: the per-cell lists of the paper, laid out
+ * supercell by supercell.
  * ------------------------------------------------------------------------- */
 int64_t orc_sort_key(const orc_grid* g, const double x[3]) {
     const int64_t S = g->S;
@@ -439,40 +438,20 @@ int64_t orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
     if (n <= 0) return 0;
     const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
     const int64_t nkeys = ncell + (g->absorb_x ? 1 : 0);   /* key ncell: removed */
-    const int64_t S3 = g->S * g->S * g->S;
-    const int64_t nsc = ncell / S3;
     int64_t* key = (int64_t*)malloc((size_t)n * sizeof(int64_t));
-    int64_t* cnt = (int64_t*)calloc((size_t)nkeys, sizeof(int64_t));
-    int64_t* start = (int64_t*)malloc(((size_t)nkeys + 1) * sizeof(int64_t));
-    int64_t* fill = (int64_t*)malloc((size_t)nkeys * sizeof(int64_t));
-    int64_t* sorted = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* start = (int64_t*)calloc((size_t)nkeys + 1, sizeof(int64_t));
     int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
     double* tmp = (double*)malloc((size_t)n * sizeof(double));
     int64_t* itmp = (int64_t*)malloc((size_t)n * sizeof(int64_t));
-    /* stable counting sort by key: every cell's particles in previous order */
+    /* stable counting sort by key */
     for (int64_t p = 0; p < n; ++p) {
         double xp[3] = {x[p], y[p], z[p]};
         key[p] = orc_sort_key(g, xp);
-        cnt[key[p]] += 1;
+        start[key[p] + 1] += 1;
     }
-    start[0] = 0;
-    for (int64_t k = 0; k < nkeys; ++k) start[k + 1] = start[k] + cnt[k];
-    for (int64_t k = 0; k < nkeys; ++k) fill[k] = start[k];
-    for (int64_t p = 0; p < n; ++p) sorted[fill[key[p]]++] = p;
-    /* interleave the cells of each supercell in rounds */
-    int64_t pos = 0;
-    for (int64_t sc = 0; sc < nsc; ++sc) {
-        int64_t maxc = 0;
-        for (int64_t l = 0; l < S3; ++l)
-            if (cnt[sc * S3 + l] > maxc) maxc = cnt[sc * S3 + l];
-        for (int64_t r = 0; r < maxc; ++r)
-            for (int64_t l = 0; l < S3; ++l) {
-                const int64_t k = sc * S3 + l;
-                if (cnt[k] > r) perm[pos++] = sorted[start[k] + r];
-            }
-    }
-    const int64_t kept = pos;
-    for (int64_t r = start[ncell]; r < n; ++r) perm[pos++] = sorted[r];   /* removed, at the end */
+    for (int64_t k = 0; k < nkeys; ++k) start[k + 1] += start[k];   /* first slot of each key */
+    const int64_t kept = start[ncell];          /* removed particles sort after every cell */
+    for (int64_t p = 0; p < n; ++p) perm[start[key[p]]++] = p;     /* previous order kept */
     permute_d(x, perm, n, tmp);
     permute_d(y, perm, n, tmp);
     permute_d(z, perm, n, tmp);
@@ -481,7 +460,7 @@ int64_t orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
     permute_d(uz, perm, n, tmp);
     for (int64_t i = 0; i < n; ++i) itmp[i] = id[perm[i]];
     memcpy(id, itmp, (size_t)n * sizeof(int64_t));
-    free(key); free(cnt); free(start); free(fill); free(sorted); free(perm); free(tmp); free(itmp);
+    free(key); free(start); free(perm); free(tmp); free(itmp);
     return kept;
 }
 
@@ -564,9 +543,11 @@ void orc_divb(const orc_grid* g, const double* const B[3], double* out) {
 double orc_kinetic(double m, double w, int64_t n, const double* ux, const double* uy,
                    const double* uz) {
     double s = 0.0;
+    /* gamma - 1 = u^2 / (1 + sqrt(1 + u^2)), free of the cancellation of
+     * sqrt(1 + u^2) - 1 for slow particles */
     for (int64_t p = 0; p < n; ++p) {
-        double gam = sqrt(1.0 + ((ux[p] * ux[p] + uy[p] * uy[p]) + uz[p] * uz[p]));
-        s += gam - 1.0;
+        double u2 = (ux[p] * ux[p] + uy[p] * uy[p]) + uz[p] * uz[p];
+        s += u2 / (1.0 + sqrt(1.0 + u2));
     }
     return w * m * s;
 }

@@ -90,11 +90,11 @@ void orc_add_laser(const orc_grid* g, double* Jy, int64_t plane, double E0, doub
 /* Sort key (supercell-major, then local cell) of one in-domain position. */
 int64_t orc_sort_key(const orc_grid* g, const double x[3]);
 
-/* Re-sort of n particles: stable sort by orc_sort_key, then inside every
- * supercell the cells' particles interleaved in rounds (round r: the r-th
- * particle of each cell with more than r, in cell order).  Permutes the six
- * state arrays and id in place; removed particles (absorbing x) go to the
- * end in their previous order.  Returns the number of particles kept. */
+/* Re-sort of n particles: stable sort by orc_sort_key (every cell's
+ * particles together in their previous order, cells grouped by supercell).
+ * Permutes the six state arrays and id in place; removed particles
+ * (absorbing x) go to the end in their previous order.  Returns the number of
+ * particles kept. */
 int64_t orc_rebin(const orc_grid* g, int64_t n, double* x, double* y, double* z,
                double* ux, double* uy, double* uz, int64_t* id);
 

@@ -53,7 +53,9 @@ __global__ void __launch_bounds__(kBlock) kinetic_kernel(const double* ux, const
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
         if (x && x[i] < 0.0) continue;       // removed (absorbing x)
-        s += sqrt(1.0 + ((ux[i] * ux[i] + uy[i] * uy[i]) + uz[i] * uz[i])) - 1.0;
+        // gamma - 1 without the cancellation of sqrt(1 + u^2) - 1 at small u
+        const double u2 = (ux[i] * ux[i] + uy[i] * uy[i]) + uz[i] * uz[i];
+        s += u2 / (1.0 + sqrt(1.0 + u2));
         live += 1.0;
     }
     s = block_sum(s, red);

@@ -13,7 +13,7 @@ import sys
 
 import numpy as np
 
-import oracle
+from gpu_layout import LayoutOracle
 from paper_1608_01009_amd import pic
 
 KEYS = ("x", "y", "z", "ux", "uy", "uz", "id")
@@ -26,8 +26,8 @@ def log(*a):
 
 
 def oracle_for(wl):
-    return oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
-                            S=wl.S, R=wl.R)
+    return LayoutOracle(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+                        S=wl.S, R=wl.R)
 
 
 def read_state(sim, nspecies):

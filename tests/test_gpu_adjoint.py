@@ -29,6 +29,7 @@ import numpy as np
 import pytest
 
 import oracle
+from gpu_layout import LayoutOracle
 from paper_1608_01009_amd import pic
 from paper_1608_01009_amd import workloads as W
 
@@ -44,7 +45,7 @@ def _state(sim, nsp):
 
 
 def _oracle_from(wl, species, F, P, R, since=0):
-    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, species, S=wl.S, R=R)
+    o = LayoutOracle(wl.n, wl.dx, wl.dt, species, S=wl.S, R=R)
     o.set_state([[p[k][:p["n"]] for k in KEYS] for p in P], F[:6], since)
     return o
 
@@ -368,7 +369,7 @@ def test_autograd_probe_energy_and_kinetic_energy_losses():
     gP = [p.grad.cpu().numpy() for p in Pg]
     assert sim.counters()[1] == 3
     # the oracle's adjoint from the same initial state and the analytic seeds
-    o = oracle.OracleSim(n, (1.0, 1.0, 1.0), 0.5, species, S=4, R=R)
+    o = LayoutOracle(n, (1.0, 1.0, 1.0), 0.5, species, S=4, R=R)
     for s, p in enumerate(parts):
         o.load_particles(s, *p)
     o.set_fields([a for a in EB0(a0).cpu().numpy()])

@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
+from gpu_layout import LayoutOracle
 from paper_1608_01009_amd import pic
 from paper_1608_01009_amd import workloads as W
 
@@ -41,7 +42,7 @@ def _small_slab(seed=21):
 
 
 def _oracle(wl, F, P, k):
-    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+    o = LayoutOracle(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
                          S=wl.S, R=wl.R, absorb_x=True, laser=wl.laser)
     o.set_state([[p[k_][:p["n"]] for k_ in KEYS] for p in P], F[:6], k % wl.R, step_count=k)
     return o
@@ -124,7 +125,7 @@ def test_laser_in_vacuum_matches_oracle():
     sim = pic.Simulation.from_workload(wl)
     sim.step(300)
     F = sim.fields()
-    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+    o = LayoutOracle(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
                          S=wl.S, R=wl.R, absorb_x=True, laser=wl.laser)
     for s in range(2):
         o.load_particles(s, *[np.zeros(0)] * 6)

@@ -22,7 +22,7 @@ from paper_1608_01009_amd import workloads as W
 
 from gpu_parity_util import KEYS, log, read_state
 
-import oracle
+from gpu_layout import LayoutOracle
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ EPS32 = 2.0 ** -24
 
 
 def _mixed_oracle(wl, precision="mixed"):
-    o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
+    o = LayoutOracle(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
                          S=wl.S, R=wl.R, precision=precision)
     o.collect_abs = precision == "mixed"
     return o

@@ -1,7 +1,9 @@
 """Pins of the oracle's energy sums against exact special values.
 
 * Kinetic energy w m (gamma - 1): u = 0.75 gives gamma = 1.25 exactly; u = 2.4
-  gives gamma = 2.6; small u approaches w m u^2 / 2.
+  gives gamma = 2.6; for slow particles (|u| = 1e-3 .. 1e-9) gamma - 1 keeps
+  full relative accuracy against a 50-digit evaluation (the form
+  sqrt(1 + u^2) - 1 loses it to cancellation).
 * Field energy 1/2 sum F^2 dV: a cosine of one full period on the lattice sums
   to exactly half the number of points (discrete orthogonality).
 """
@@ -29,6 +31,19 @@ def test_kinetic_small_u_limit(orc):
     z = np.zeros(1)
     K = L.orc_kinetic(2.0, 1.5, 1, orc._dp(u), orc._dp(z), orc._dp(z))
     assert abs(K - 0.5 * 3.0 * 1e-8) < 1e-16
+
+
+def test_kinetic_slow_particles_full_relative_accuracy(orc):
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    L = orc.lib()
+    for u0 in (1e-3, 3.7e-5, 1e-7, 2.2e-9):
+        u = np.array([u0, 0.6 * u0, 0.0])
+        ux, uy, uz = (np.ascontiguousarray(u[i:i + 1]) for i in range(3))
+        K = L.orc_kinetic(1.0, 1.0, 1, orc._dp(ux), orc._dp(uy), orc._dp(uz))
+        u2 = Decimal(float(u[0])) ** 2 + Decimal(float(u[1])) ** 2
+        want = float((1 + u2).sqrt() - 1)
+        assert abs(K - want) <= 4e-16 * want, (u0, K, want)
 
 
 def test_field_energy_of_a_lattice_cosine(orc):

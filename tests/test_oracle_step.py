@@ -13,9 +13,11 @@ Section 3: charge-conserving deposition; Section 4.3: supercell grouping).
   For k = 2 pi / 16 the alias-free value is 0.99380 and the bare leapfrog
   value 1.00351; the measured value matches the alias sum to 1e-5 for the
   three lowest modes.
-* Rebin: the stored order groups particles by supercell and interleaves the
-  cells of a supercell in rounds; recomputed here with numpy as a sort by
-  the composite key (supercell, rank in cell, cell).
+* Rebin: the stored order is the paper's per-cell storage grouped by
+  supercells, i.e. numpy's stable argsort of the (supercell, cell) key.
+  The GPU library's round-interleaved layout of the same lists is a
+  test-side permutation (tests/gpu_layout.py), pinned here against its
+  definition written out as loops.
 """
 import math
 
@@ -130,7 +132,14 @@ def test_cold_plasma_oscillation_frequency(orc, mode):
         assert abs(p[1] - _discrete_cold_omega(k, dt, other)) > 1e-3
 
 
-def test_rebin_order_supercell_rounds(orc):
+def _keys(n, S, P):
+    c = np.floor(P).astype(np.int64)
+    ns = [n[d] // S for d in range(3)]
+    return ((c[:, 0] // S + ns[0] * (c[:, 1] // S + ns[1] * (c[:, 2] // S))) * S ** 3
+            + (c[:, 0] % S + S * (c[:, 1] % S + S * (c[:, 2] % S))))
+
+
+def test_rebin_order_is_stable_sort_by_supercell_and_cell(orc):
     n, S = (8, 12, 4), 4
     rng = np.random.default_rng(9)
     N = 3000
@@ -141,19 +150,8 @@ def test_rebin_order_supercell_rounds(orc):
     ids = rng.permutation(N).astype(np.int64)
     sim = orc.OracleSim(n, (1.0, 1.0, 1.0), 0.2, [(-1.0, 1.0, 0.1)], S=S, R=20)
     sim.load_particles(0, P[:, 0], P[:, 1], P[:, 2], u[:, 0], u[:, 1], u[:, 2], ids)
-    c = np.floor(P).astype(np.int64)
-    ns = [n[d] // S for d in range(3)]
-    key = ((c[:, 0] // S + ns[0] * (c[:, 1] // S + ns[1] * (c[:, 2] // S))) * S ** 3
-           + (c[:, 0] % S + S * (c[:, 1] % S + S * (c[:, 2] % S))))
-    # independent formulation of the stored order: sort by the composite key
-    # (supercell, rank of the particle among its cell's particles in input
-    # order, cell in supercell)
-    S3 = S ** 3
-    order1 = np.argsort(key, kind="stable")
-    sk = key[order1]
-    rank = np.empty(N, dtype=np.int64)
-    rank[order1] = np.arange(N) - np.searchsorted(sk, sk, side="left")
-    perm = np.lexsort((key % S3, rank, key // S3))
+    key = _keys(n, S, P)
+    perm = np.argsort(key, kind="stable")
     got = sim.particles(0)
     assert np.array_equal(got["id"], ids[perm])
     assert np.array_equal(got["x"], P[perm, 0]) and np.array_equal(got["uz"], u[perm, 2])
@@ -163,9 +161,10 @@ def test_rebin_order_supercell_rounds(orc):
         assert orc.sort_key(g, P[p]) == key[p]
 
 
-def test_rebin_order_clustered_and_rounds_structure(orc):
-    """Very uneven cell counts (one cell holds most particles): the rounds end
-    with the crowded cell's particles alone, in input order."""
+def test_rebin_order_clustered(orc):
+    """Very uneven cell counts (one cell holds most particles): that cell's
+    particles form one contiguous run in input order, between the cells
+    before and after it."""
     n, S = (4, 4, 8), 4
     rng = np.random.default_rng(10)
     N = 400
@@ -177,12 +176,48 @@ def test_rebin_order_clustered_and_rounds_structure(orc):
     sim = orc.OracleSim(n, (1.0, 1.0, 1.0), 0.2, [(-1.0, 1.0, 0.1)], S=S, R=20)
     sim.load_particles(0, P[:, 0], P[:, 1], P[:, 2], z, z, z, ids)
     got = sim.particles(0)["id"]
-    # the crowded cell (1, 2, 6) -> supercell 1; its particles appear in input
-    # order, and the last ones form single-particle rounds at the very end
-    crowded = [i for i in got if i < 300]
-    assert crowded == sorted(crowded)
-    c = np.floor(P[got]).astype(int)
-    sc = (c[:, 2] // 4)
-    assert np.all(np.diff(sc) >= 0)
-    tail = got[-150:]
-    assert np.all(tail < 300)
+    key = _keys(n, S, P[got])
+    assert np.all(np.diff(key) >= 0)
+    crowded = np.flatnonzero(key == _keys(n, S, np.array([[1.5, 2.5, 6.5]]))[0])
+    run = got[crowded]
+    assert len(run) >= 300 and np.all(np.diff(crowded) == 1)
+    assert np.all(np.diff(run) > 0)                   # input order kept
+
+
+def _interleave_by_loops(keys, S3):
+    """The round-interleaved layout written out from its definition: inside
+    each supercell, round r takes the r-th particle (per-cell order) of every
+    cell with more than r particles, cells in increasing order."""
+    out = []
+    cells = {}
+    for i, k in enumerate(keys):
+        cells.setdefault(int(k), []).append(i)
+    for sc in sorted({int(k) // S3 for k in keys}):
+        lists = [cells.get(sc * S3 + l, []) for l in range(S3)]
+        for r in range(max(len(c) for c in lists)):
+            for c in lists:
+                if len(c) > r:
+                    out.append(c[r])
+    return np.array(out, dtype=np.int64)
+
+
+def test_gpu_layout_comparator_matches_its_definition(orc):
+    """The test-side permutation to the GPU layout (a composite-key sort)
+    equals the loop construction, on random, clustered and sparse inputs,
+    and the layout oracle stores exactly the oracle's particles in it."""
+    from gpu_layout import LayoutOracle, round_interleave, sort_keys
+    rng = np.random.default_rng(11)
+    for n, S, N in (((8, 12, 4), 4, 3000), ((4, 4, 8), 2, 500), ((8, 8, 8), 4, 37)):
+        P = rng.random((N, 3)) * np.array(n)
+        P[: N // 3] = np.array(n) * 0.3 + rng.uniform(-0.5, 0.5, (N // 3, 3))
+        key = np.sort(sort_keys(n, S, P[:, 0], P[:, 1], P[:, 2]))
+        assert np.array_equal(round_interleave(key, S ** 3), _interleave_by_loops(key, S ** 3))
+        ids = rng.permutation(N).astype(np.int64)
+        z = np.zeros(N)
+        plain = orc.OracleSim(n, (1.0, 1.0, 1.0), 0.2, [(-1.0, 1.0, 0.1)], S=S, R=20)
+        lay = LayoutOracle(n, (1.0, 1.0, 1.0), 0.2, [(-1.0, 1.0, 0.1)], S=S, R=20)
+        for o in (plain, lay):
+            o.load_particles(0, P[:, 0], P[:, 1], P[:, 2], z, z, z, ids)
+        pid = plain.particles(0)["id"]
+        pk = sort_keys(n, S, *[plain.particles(0)[k] for k in ("x", "y", "z")])
+        assert np.array_equal(lay.particles(0)["id"], pid[_interleave_by_loops(pk, S ** 3)])
