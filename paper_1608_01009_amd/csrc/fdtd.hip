@@ -230,17 +230,22 @@ __device__ __forceinline__ int lin_abs(const AbsArgs& a, int i, int j, int k) {
 }
 
 // Bo = B - dt/2 curl E; the slot n0-1 of By, Bz (outside) is zero.  Bo may
-// equal B (each thread reads and writes its own cell only).
+// equal B (each thread reads and writes its own cell only).  Jy, when not
+// null, receives the laser sheet's current on its plane: the E update has
+// already consumed it (as a term of its own), and the stored J of the step
+// includes the source.  No kernel of the update reads J after the E pass, so
+// that write cannot race with a read.
 __global__ void __launch_bounds__(kBlock) abs_half_b_kernel(AbsArgs a, const double* Ex,
                                                            const double* Ey, const double* Ez,
                                                            const double* Bx, const double* By,
                                                            const double* Bz, double* Box,
-                                                           double* Boy, double* Boz) {
+                                                           double* Boy, double* Boz, double* Jy) {
 #pragma clang fp contract(off)
     const int nx = a.n[0], ncell = a.n[0] * a.n[1] * a.n[2];
     const double dx = a.dx[0], dy = a.dx[1], dz = a.dx[2];
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
         const int i = c % nx, j = (c / nx) % a.n[1], k = c / (nx * a.n[1]);
+        if (Jy && i == a.plane) Jy[c] = Jy[c] + a.laser;
         const double cx = (Ez[lin_abs(a, i, j + 1, k)] - Ez[c]) / dy -
                           (Ey[lin_abs(a, i, j, k + 1)] - Ey[c]) / dz;
         Box[c] = Bx[c] - a.hdt * cx;
@@ -263,7 +268,8 @@ struct Ey2 {
 };
 
 // E_y, E_z after the curl update at an inside plane 1 <= i <= n0-2 (the laser
-// sheet's current added to Jy on its plane)
+// sheet's current added to the deposited Jy on its plane; J itself is only
+// read here)
 __device__ __forceinline__ Ey2 e_inside(const AbsArgs& a, int i, int j, int k,
                                         const double* const E[3], const double* const B[3],
                                         const double* const J[3]) {
@@ -282,8 +288,9 @@ __device__ __forceinline__ Ey2 e_inside(const AbsArgs& a, int i, int j, int k,
 __global__ void __launch_bounds__(kBlock) abs_e_kernel(AbsArgs a, const double* E0,
                                                       const double* E1, const double* E2,
                                                       const double* B0, const double* B1,
-                                                      const double* B2, double* J0, double* J1,
-                                                      double* J2, double* Eo0, double* Eo1,
+                                                      const double* B2, const double* J0,
+                                                      const double* J1, const double* J2,
+                                                      double* Eo0, double* Eo1,
                                                       double* Eo2, double* Jc0, double* Jc1,
                                                       double* Jc2) {
 #pragma clang fp contract(off)
@@ -314,7 +321,6 @@ __global__ void __launch_bounds__(kBlock) abs_e_kernel(AbsArgs a, const double* 
             Eo1[c] = e.y;
             Eo2[c] = e.z;
         }
-        if (i == a.plane) J1[c] = J[1][c] + a.laser;   // the source is part of this step's J
         Jc0[c] = 0.0;
         Jc1[c] = 0.0;
         Jc2[c] = 0.0;
@@ -338,12 +344,14 @@ hipError_t launch_fdtd_absorbing(const Geom& g, const Fields& f, const Fields& f
     int nb = (g.ncell + kBlock - 1) / kBlock;
     if (nb > 65536) nb = 65536;
     hipLaunchKernelGGL(abs_half_b_kernel, dim3(nb), dim3(kBlock), 0, s, a, f.E[0], f.E[1],
-                       f.E[2], f.B[0], f.B[1], f.B[2], fo.B[0], fo.B[1], fo.B[2]);
+                       f.E[2], f.B[0], f.B[1], f.B[2], fo.B[0], fo.B[1], fo.B[2],
+                       (double*)nullptr);
     hipLaunchKernelGGL(abs_e_kernel, dim3(nb), dim3(kBlock), 0, s, a, f.E[0], f.E[1], f.E[2],
                        fo.B[0], fo.B[1], fo.B[2], J[0], J[1], J[2], fo.E[0], fo.E[1], fo.E[2],
                        Jclear[0], Jclear[1], Jclear[2]);
     hipLaunchKernelGGL(abs_half_b_kernel, dim3(nb), dim3(kBlock), 0, s, a, fo.E[0], fo.E[1],
-                       fo.E[2], fo.B[0], fo.B[1], fo.B[2], fo.B[0], fo.B[1], fo.B[2]);
+                       fo.E[2], fo.B[0], fo.B[1], fo.B[2], fo.B[0], fo.B[1], fo.B[2],
+                       laser_plane >= 0 ? J[1] : (double*)nullptr);
     return hipGetLastError();
 }
 

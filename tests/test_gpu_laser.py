@@ -116,6 +116,33 @@ def test_laser_slab_two_species_one_launch_parity():
     sim.close()
 
 
+@pytest.mark.parametrize("plane", [1, 18])
+def test_laser_sheet_next_to_a_mur_plane_parity(plane):
+    """The source sheet on the plane next to a Mur plane (1 or n0 - 2) on a
+    box 20 cells wide: the Mur update of the boundary plane recomputes its
+    neighbour's new E_y from that plane's J, and on this width some rows of
+    the two planes fall into different waves.  The one-step protocol checks
+    that the source enters E_y once and the stored J once."""
+    wl = W.laser_slab(n=(20, 8, 8), slab=(6, 14), ppc=2, seed=31, wavelength=8.0,
+                      envelope_steps=60, plane=plane, name=f"laser-plane-{plane}")
+    sim = pic.Simulation.from_workload(wl)
+    at = 0
+    for k in (0, 5, 19, 20, 33):
+        if k > at:
+            sim.step(k - at)
+            at = k
+        F0, P0 = _state(sim, 2)
+        sim.step(1)
+        at += 1
+        F1, P1 = _state(sim, 2)
+        o = _oracle(wl, F0, P0, k)
+        o.step(1)
+        rep = compare(F1, P1, o, wl.n, tag=f"plane {plane} step {k}")
+        log(f"  plane {plane} step {k} -> {k + 1}: Ey {rep['Ey']:.2e} Jy {rep['Jy']:.2e}")
+    assert np.max(np.abs(sim.fields()[1])) > 0.1 * wl.laser[0]    # the pulse is in the box
+    sim.close()
+
+
 def test_laser_in_vacuum_matches_oracle():
     n = (96, 4, 4)
     wl = W.laser_slab(n=n, slab=(40, 44), ppc=1, wavelength=16.0, name="vacuum")
