@@ -34,11 +34,16 @@ struct SpeciesState {
     SpeciesM cm{};             // FP32 constants of the mixed-precision push
     int cur = 0;               // buffer holding the particles
     int* sc_off = nullptr;     // supercell offsets of the (new) order
+    int* sc_prev = nullptr;    // supercell offsets of the order before the last re-sort
     unsigned* keys = nullptr;  // sort keys written by the push before a re-sort
     unsigned* perm = nullptr;  // re-sort order: new index -> index in buf[cur]
     bool pending = false;      // buf[cur] is still in the old order; apply perm
     bool loaded = false;
 };
+
+// Mean particles per supercell from which a pending re-sort order is applied
+// by the staged permutation rather than read through by the push.
+constexpr int64_t kStagedPermuteMin = 1024;
 
 enum Stage { ST_PUSH = 0, ST_PUSH_PERM = 1, ST_FAR = 2, ST_FDTD = 3, ST_SORT = 4, ST_TOTAL = 5,
              ST_N = 6 };
@@ -280,6 +285,8 @@ int compute_refs(pic_ctx* c) {
 // Order of the next re-sort from the keys written by the last push (or from
 // the positions when keys == nullptr); the data move with the next push.
 int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys) {
+    HIPCHK(c, hipMemcpyAsync(s.sc_prev, s.sc_off, (size_t)(c->g.nsc + 1) * sizeof(int),
+                             hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, launch_sort(c->g, s.n, keys, s.buf[s.cur], s.perm, s.sc_off, c->scratch, c->d_err,
                           c->stream));
     s.pending = true;
@@ -369,6 +376,17 @@ int step_once(pic_ctx* c) {
         if (pair) break;
         if (s.n == 0) continue;
         const bool mixed = c->precision == PIC_FP32_MIXED;
+        if (s.pending && !mixed && !c->g.absorb_x && s.n >= (int64_t)kStagedPermuteMin * c->g.nsc) {
+            // dense supercells: the re-sort order is applied by a permutation
+            // staged through LDS, and the push reads in stored order (reading
+            // through the order instead touches about twelve times the cache
+            // lines per load when a supercell holds thousands of particles)
+            Timed t(c, ST_SORT);
+            HIPCHK(c, launch_staged_permute(c->g, s.n, s.perm, s.sc_prev, s.sc_off, s.buf[s.cur],
+                                            s.buf[1 - s.cur], c->stream));
+            s.cur = 1 - s.cur;
+            s.pending = false;
+        }
         const Parts& src = s.buf[s.cur];
         const Parts& dst = s.pending ? s.buf[1 - s.cur] : s.buf[s.cur];
         const PartsM& srcm = s.bufm[s.cur];
@@ -812,6 +830,7 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
             P.spare = (unsigned)q.capacity;
         }
         if ((e = dalloc(c, (void**)&st.sc_off, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess ||
+            (e = dalloc(c, (void**)&st.sc_prev, (size_t)(g.nsc + 1) * sizeof(int))) != hipSuccess ||
             (e = dalloc(c, (void**)&st.keys, (size_t)q.capacity * sizeof(unsigned))) != hipSuccess ||
             (e = dalloc(c, (void**)&st.perm, (size_t)q.capacity * sizeof(unsigned))) != hipSuccess)
             return cfail(hip_fail(c, e, "hipMalloc sc_off / keys / perm"));

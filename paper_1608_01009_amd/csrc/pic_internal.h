@@ -197,6 +197,12 @@ hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, con
                           hipStream_t s);
 hipError_t launch_permute_ids(int64_t n, const unsigned* perm, const int64_t* src, int64_t* dst,
                               hipStream_t s);
+// The same permutation for a re-sort whose old order had the supercell
+// offsets old_off (each supercell's particles, mostly in one old block, are
+// staged through LDS); new_off: the offsets of the new order.
+hipError_t launch_staged_permute(const Geom& g, int64_t n, const unsigned* perm, const int* old_off,
+                                const int* new_off, const Parts& src, const Parts& dst,
+                                hipStream_t s);
 
 // Adjoint of one step (FP64).  launch_fdtd_adjoint: the transposed Yee update
 // in place on (lE, lB), writing lJ (the adjoint of the step's current).

@@ -84,46 +84,63 @@ struct PDMulti {
     PDArgs s[NSP];
 };
 
-// One straight segment A->B inside the cell with integer corner `cell`
-// (Villasenor-Buneman): for J_d, the four edges of the d-directed cell edges
-// receive jc_d * delta_d * W with W = w_p w_r +- delta_p delta_r / 12 at the
-// segment midpoint.  `sink(d, i, j, k, v)` adds v to J_d at the edge whose
-// integer corner is lattice node (i, j, k) (unwrapped).
+// Villasenor-Buneman current of one straight segment a -> b inside one cell,
+// in cell-local coordinates (a, b in [0, 1]^3, both computed exactly from
+// the positions).  J_d receives at the four d-directed edges of the cell
+// jc_d dl_d W with W = w_p w_r +- dl_p dl_r / 12 (w at the segment midpoint,
+// 1 - m or m per edge, p < r the transverse axes); the cross term
+// jc_d dl_d dl_p dl_r / 12 is the same triple product dl_x dl_y dl_z for all
+// three components.  emit(j, v) receives contribution j = 4 d + 2 bp + br
+// (bp, br: the edge's offset along p and r).  J is summed by atomics in any
+// order, so only the value of each contribution, not its rounding, is fixed.
+template <class Emit>
+__device__ __forceinline__ void vb_cell(const double a[3], const double b[3], const double jc[3],
+                                        const Emit& emit) {
+    double dl[3], m[3], w[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        dl[d] = b[d] - a[d];
+        m[d] = 0.5 * (a[d] + b[d]);
+        w[d] = 1.0 - m[d];
+    }
+    const double P = (dl[0] * dl[1]) * (dl[2] * (1.0 / 12.0));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int p = d == 0 ? 1 : 0;
+        const int r = d == 2 ? 1 : 2;
+        const double f = jc[d] * dl[d];
+        const double A = f * w[p], B = f * m[p], X = jc[d] * P;
+        emit(4 * d + 0, __fma_rn(A, w[r], X));
+        emit(4 * d + 1, __fma_rn(A, m[r], -X));
+        emit(4 * d + 2, __fma_rn(B, w[r], -X));
+        emit(4 * d + 3, __fma_rn(B, m[r], X));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// One straight segment A->B inside the cell with integer corner `cell`:
+// `sink(d, i, j, k, v)` adds v to J_d at the edge whose integer corner is
+// lattice node (i, j, k) (unwrapped).
 template <class Sink>
 __device__ __forceinline__ void vb_segment(const double A[3], const double B[3],
                                            const int cell[3], const double jc[3],
                                            const Sink& sink) {
 #pragma clang fp contract(off)
-    double a[3], b[3], dl[3], m[3];
+    double a[3], b[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         a[d] = A[d] - (double)cell[d];
         b[d] = B[d] - (double)cell[d];
-        dl[d] = b[d] - a[d];
-        m[d] = 0.5 * (a[d] + b[d]);
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
-        const int p = e1 < e2 ? e1 : e2;
-        const int r = e1 < e2 ? e2 : e1;
-        const double cross = (dl[p] * dl[r]) * (1.0 / 12.0);
-        const double flux = jc[d] * dl[d];
-#pragma unroll
-        for (int bp = 0; bp < 2; ++bp) {
-            const double wp = bp ? m[p] : 1.0 - m[p];
-#pragma unroll
-            for (int br = 0; br < 2; ++br) {
-                const double wr = br ? m[r] : 1.0 - m[r];
-                const double W = wp * wr + ((bp == br) ? cross : -cross);
-                int o[3] = {0, 0, 0};
-                o[p] = bp;
-                o[r] = br;
-                sink(d, cell[0] + o[0], cell[1] + o[1], cell[2] + o[2], flux * W);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    vb_cell(a, b, jc, [&](int j, double v) {
+        const int d = j >> 2, bp = (j >> 1) & 1, br = j & 1;
+        const int p = d == 0 ? 1 : 0;
+        const int r = d == 2 ? 1 : 2;
+        int o[3] = {0, 0, 0};
+        o[p] = bp;
+        o[r] = br;
+        sink(d, cell[0] + o[0], cell[1] + o[1], cell[2] + o[2], v);
+    });
 }
 
 // Sort key of a stored (wrapped) position: supercell * S^3 + cell in
@@ -292,28 +309,14 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
 template <class Add>
 __device__ __forceinline__ void vb_single(const double x0[3], const double x1[3], const int c[3],
                                           const double jc[3], const Add& add) {
-    double a[3], b[3], dl[3], m[3];
+#pragma clang fp contract(off)
+    double a[3], b[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         a[d] = x0[d] - (double)c[d];
         b[d] = x1[d] - (double)c[d];
-        dl[d] = b[d] - a[d];
-        m[d] = 0.5 * (a[d] + b[d]);
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
-        const int p = e1 < e2 ? e1 : e2;
-        const int r = e1 < e2 ? e2 : e1;
-        const double cross = (dl[p] * dl[r]) * (1.0 / 12.0);
-        const double flux = jc[d] * dl[d];
-        const double wp0 = 1.0 - m[p], wr0 = 1.0 - m[r];
-        add(4 * d + 0, flux * (wp0 * wr0 + cross));
-        add(4 * d + 1, flux * (wp0 * m[r] - cross));
-        add(4 * d + 2, flux * (m[p] * wr0 - cross));
-        add(4 * d + 3, flux * (m[p] * m[r] + cross));
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    vb_cell(a, b, jc, add);
 }
 
 // Layout of the E/B tile in LDS: node (tx, ty, tz) of component c lives at

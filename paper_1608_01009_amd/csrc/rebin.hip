@@ -331,9 +331,21 @@ __global__ void __launch_bounds__(kBlock) interleave_kernel(const unsigned* __re
     }
 }
 
-__global__ void __launch_bounds__(kBlock) permute_kernel(int n, const unsigned* perm, Parts src,
-                                                         Parts dst) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Give each XCD a contiguous range of blocks: the gathered reads of one
+// supercell's particles (old slots close to each other) then share one L2.
+__device__ __forceinline__ int xcd_range_block(int b, int nb) {
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// dst[i] = src[perm[i]] for the six state arrays and the ids; each XCD takes
+// a contiguous range of the new order, so that the gathered reads of the
+// supercells in flight on it (old slots close to each other) share its L2.
+__global__ void __launch_bounds__(kBlock) permute_kernel(int n, const unsigned* __restrict__ perm,
+                                                         Parts src, Parts dst) {
+    const int b = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
+    for (int i = b * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const unsigned j = perm[i];
         dst.x[i] = src.x[j];
         dst.y[i] = src.y[j];
@@ -345,14 +357,6 @@ __global__ void __launch_bounds__(kBlock) permute_kernel(int n, const unsigned* 
     }
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Give each XCD a contiguous range of blocks: the gathered reads of one
-// supercell's particles (old slots close to each other) then share one L2.
-__device__ __forceinline__ int xcd_range_block(int b, int nb) {
-    if ((nb & 7) != 0) return b;
-    return (b & 7) * (nb >> 3) + (b >> 3);
-}
-
 __global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n,
                                                              const unsigned* __restrict__ perm,
                                                              const int64_t* __restrict__ src,
@@ -360,6 +364,51 @@ __global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n,
     const int b = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
     for (int i = b * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         dst[i] = src[perm[i]];
+}
+
+// dst[i] = src[perm[i]] for the six state arrays and the ids, one workgroup
+// per supercell of the new order: most of a supercell's particles were in
+// the same supercell before (its old block [old_off[s], old_off[s + 1])),
+// so each array's old block is first copied into LDS with coalesced reads,
+// and the new block is then written with coalesced stores, its values taken
+// from LDS or, for the particles that arrived from other supercells (and
+// the part of an old block beyond the LDS buffer), from global memory.
+constexpr int kStageBlock = 512;
+constexpr int kStage = 4096;   // 8-byte values per array held in LDS
+
+__global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
+    const unsigned* __restrict__ perm, const int* __restrict__ old_off,
+    const int* __restrict__ new_off, Parts src, Parts dst) {
+    __shared__ unsigned long long stage[kStage];
+    const int s = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
+    const int n0 = new_off[s], n1 = new_off[s + 1];
+    if (n0 >= n1) return;
+    const int o0 = old_off[s];
+    const int o1 = old_off[s + 1];
+    const unsigned cap = (unsigned)min(o1 - o0, kStage);
+    const unsigned long long* sa[7] = {
+        (const unsigned long long*)src.x,  (const unsigned long long*)src.y,
+        (const unsigned long long*)src.z,  (const unsigned long long*)src.ux,
+        (const unsigned long long*)src.uy, (const unsigned long long*)src.uz,
+        (const unsigned long long*)src.id};
+    unsigned long long* da[7] = {
+        (unsigned long long*)dst.x,  (unsigned long long*)dst.y,  (unsigned long long*)dst.z,
+        (unsigned long long*)dst.ux, (unsigned long long*)dst.uy, (unsigned long long*)dst.uz,
+        (unsigned long long*)dst.id};
+#pragma unroll 1
+    for (int a = 0; a < 7; ++a) {
+        const unsigned long long* __restrict__ sp = sa[a];
+        unsigned long long* __restrict__ dp = da[a];
+        for (unsigned t = threadIdx.x; t < cap; t += kStageBlock) stage[t] = sp[o0 + (int)t];
+        __syncthreads();
+#pragma unroll 4
+        for (int i = n0 + (int)threadIdx.x; i < n1; i += kStageBlock) {
+            const unsigned j = perm[i];
+            const unsigned u = j - (unsigned)o0;
+            dp[i] = u < cap ? stage[u] : sp[j];
+        }
+        __syncthreads();
+    }
 }
 
 int nblk(int64_t n, int per) {
@@ -507,6 +556,15 @@ hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, con
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, (int)n, perm, src,
                        dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_staged_permute(const Geom& g, int64_t n, const unsigned* perm, const int* old_off,
+                                const int* new_off, const Parts& src, const Parts& dst,
+                                hipStream_t s) {
+    if (n <= 0 || g.nsc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(staged_permute_kernel, dim3(g.nsc), dim3(kStageBlock), 0, s, perm, old_off,
+                       new_off, src, dst);
     return hipGetLastError();
 }
 

@@ -114,3 +114,13 @@ def test_fields_only_vacuum_step():
     wl = W.Workload("vacuum", n, (1.0, 1.0, 1.0), W.courant_dt(), 2, 20, 5,
                     [W.Species(-1.0, 1.0, 0.1, z0, z0, z0, z0, z0, z0)], fields)
     one_step_parity(wl, [0, 1, 3])[1].close()
+
+
+@pytest.mark.parametrize("n,ppc", [((16, 16, 16), 64), ((8, 8, 8), 200)])
+def test_dense_supercells_staged_resort(n, ppc):
+    # 4,096 and 12,800 particles per 4^3 supercell: the re-sort order is
+    # applied by the LDS-staged permutation (the second case also overflows
+    # its 4,096-value buffer); steps 19 (ends with the re-sort), 20 (the push
+    # after it, in stored order) and 21
+    wl = W.scaled(2, n, ppc, seed=70 + ppc)
+    one_step_parity(wl, [19, 20, 21])[1].close()
