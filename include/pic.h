@@ -196,10 +196,14 @@ int pic_enable_timers(pic_ctx* ctx, int32_t mode);
  *         LDS tiles and their flush) reading the particles in stored order,
  *   ms[1] number of those launches,
  *   ms[2] the same kernel on the first step after a re-sort, reading each
- *         particle through the re-sort order (it also writes the new order),
+ *         particle through the re-sort order (it also writes the new order;
+ *         used where supercells hold on average fewer than 1024 particles),
  *   ms[3] number of those launches,
  *   ms[4] far-mover kernel (particles beyond their tile's halo),
- *   ms[5] Yee update, ms[6] re-sort (order computation and id permutation),
+ *   ms[5] Yee update, ms[6] re-sort (order computation, and the permutation
+ *         of the particle data: of the ids where the push reads through the
+ *         order, of every array where supercells hold 1024 or more on
+ *         average),
  *   ms[7] total of the pic_step calls, ms[8] number of steps, ms[9] zero. */
 int pic_get_timers(pic_ctx* ctx, double ms[10]);
 
@@ -253,8 +257,29 @@ int pic_backward(pic_ctx* ctx, const double* const seed_fields[6],
                  const double* const* seed_particles, double* const grad_fields[6],
                  double* const* grad_particles);
 
-/* Message of the last failure on ctx (or of the last failed pic_create when
- * ctx is NULL).  Owned by the library; valid until the next call. */
+/* ---- Self-check of the push's square root and division ----
+ *
+ * The relativistic Boris push (Section 2: equations of motion) takes the
+ * square root of 1 + |u|^2 and divides by it and by 1 + |t|^2; the library
+ * evaluates these with correctly rounded FP64 sequences specialised to those
+ * operand ranges (so that positions and momenta are reproducible bit for
+ * bit).  This call evaluates the same sequences on arrays, for comparison
+ * with any correctly rounded reference:
+ *   sq[i] = sqrt(x[i])   for finite x[i] >= 1,
+ *   dv[i] = a[i] / b[i]  for 1 <= b[i] < 2^1000 and a[i] = 0 or
+ *                        2^-900 < |a[i]| < 2^900;
+ * other operands give unspecified values.  n doubles per array, host or
+ * device memory (copied to and from device buffers the call allocates and
+ * frees).  x and sq NULL: no square roots; a, b and dv NULL: no divisions.
+ * PIC_EINVAL for n < 0 or a half-given pair; PIC_ENOMEM / PIC_EDEVICE for HIP
+ * failures (message: pic_last_error(NULL)).  Synchronous, on the current
+ * device; needs no context. */
+int pic_eval_sqrt_div(int64_t n, const double* x, const double* a, const double* b, double* sq,
+                      double* dv);
+
+/* Message of the last failure on ctx (or of the last failed pic_create or
+ * context-free call when ctx is NULL).  Owned by the library; valid until the
+ * next call. */
 const char* pic_last_error(const pic_ctx* ctx);
 
 /* Release the context and all its device memory.  NULL is ignored. */

@@ -660,6 +660,49 @@ int backward_sweep(pic_ctx* c, double* const lEB[6], std::vector<std::array<doub
 
 extern "C" {
 
+int pic_eval_sqrt_div(int64_t n, const double* x, const double* a, const double* b, double* sq,
+                      double* dv) {
+    g_create_error.clear();
+    const bool want_sq = x != nullptr || sq != nullptr;
+    const bool want_dv = a != nullptr || b != nullptr || dv != nullptr;
+    if (n < 0 || (want_sq && (!x || !sq)) || (want_dv && (!a || !b || !dv))) {
+        g_create_error = "pic_eval_sqrt_div: n must be >= 0 and x/sq, a/b/dv given together";
+        return PIC_EINVAL;
+    }
+    if (n == 0 || (!want_sq && !want_dv)) return PIC_OK;
+    const size_t bytes = (size_t)n * sizeof(double);
+    double* d[5] = {};
+    auto release = [&]() {
+        for (double* p : d)
+            if (p) (void)hipFree(p);
+    };
+    auto hfail = [&](hipError_t e, const char* what) {
+        g_create_error = std::string("pic_eval_sqrt_div: ") + what + ": " + hipGetErrorString(e);
+        release();
+        return e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE;
+    };
+    const double* in[3] = {x, a, b};
+    const bool use[5] = {want_sq, want_dv, want_dv, want_sq, want_dv};
+    for (int k = 0; k < 5; ++k) {
+        if (!use[k]) continue;
+        hipError_t e = hipMalloc((void**)&d[k], bytes);
+        if (e != hipSuccess) return hfail(e, "hipMalloc");
+        if (k < 3) {
+            e = hipMemcpy(d[k], in[k], bytes, hipMemcpyDefault);
+            if (e != hipSuccess) return hfail(e, "hipMemcpy");
+        }
+    }
+    hipError_t e = launch_sqrt_div(n, d[0], d[1], d[2], d[3], d[4], nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hfail(e, "kernel");
+    if (want_sq && (e = hipMemcpy(sq, d[3], bytes, hipMemcpyDefault)) != hipSuccess)
+        return hfail(e, "hipMemcpy");
+    if (want_dv && (e = hipMemcpy(dv, d[4], bytes, hipMemcpyDefault)) != hipSuccess)
+        return hfail(e, "hipMemcpy");
+    release();
+    return PIC_OK;
+}
+
 int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
                const pic_species_t* species, int32_t n_species, pic_ctx** out) {
     g_create_error.clear();

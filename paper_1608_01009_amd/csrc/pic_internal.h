@@ -221,6 +221,11 @@ hipError_t launch_particle_adjoint(const Geom& g, const SpeciesC& sp, int64_t n,
 hipError_t launch_unpermute(int64_t n, const unsigned* perm, double* const src[6],
                             double* const dst[6], hipStream_t s);
 
+// The push's correctly rounded square root (x >= 1) and division (divisor in
+// [1, 2^1000)) on device arrays; sq or dv NULL skips that part.
+hipError_t launch_sqrt_div(int64_t n, const double* x, const double* a, const double* b,
+                           double* sq, double* dv, hipStream_t s);
+
 // Diagnostics.
 hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, hipStream_t s);
 // kinetic sum of gamma - 1; with x given, particles with x < 0 (removed) are

@@ -943,6 +943,29 @@ hipError_t launch_push_deposit_pair(const Geom& g, const SpeciesC* sp, const Par
     return hipErrorInvalidValue;
 }
 
+namespace {
+
+// The push's square root and division on arrays (the library's self-check).
+__global__ void __launch_bounds__(256) sqrt_div_kernel(int64_t n, const double* x, const double* a,
+                                                      const double* b, double* sq, double* dv) {
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        if (sq) sq[i] = sqrt_ge1(x[i]);
+        if (dv) dv[i] = div_ge1(a[i], b[i]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sqrt_div(int64_t n, const double* x, const double* a, const double* b,
+                           double* sq, double* dv, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(sqrt_div_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, x, a, b, sq, dv);
+    return hipGetLastError();
+}
+
 hipError_t launch_far_movers(const Geom& g, const SpeciesC& sp, const Parts& src,
                              const Parts& dst, const unsigned* perm, unsigned* keys,
                              const Fields& f, double* const J[3], unsigned* err,

@@ -14,12 +14,17 @@ Function) against the oracle's adjoint and against finite differences.
 * the autograd Function at the 32^3 / 16 ppc workload (524,288 electrons,
   eight E_x modes, 40 steps): gradients with respect to the mode amplitudes
   and to sampled initial momenta and positions agree with central finite
-  differences of the deterministic forward run to 1e-6 (particle components:
-  at most 5 % outliers, where a kink of the piecewise-smooth step lies within
-  +-h).  Over the full 400 steps the same comparison is limited by those kinks
-  (the finite-difference error falls linearly with h, to about 1e-4 at
-  h = 1e-8); the adjoint itself is checked there through its parity with the
-  oracle's adjoint above;
+  differences of the deterministic forward run to 1e-6 relative (for the
+  particle components: plus the quotient's own noise, measured as its change
+  between h and h/2), on every component whose +-h runs take the same pieces
+  of the piecewise-smooth step (the same cells and stagger cells at every
+  step; the others are detected and counted);
+* the config-5 grid and schedule over the full 400 steps with checkpoints
+  every 20, at 2 of its 16 particles per cell: mode and momentum gradients
+  equal the oracle's recorded-run adjoint.  Over 400 steps a finite-difference
+  check is limited by the kinks (its error falls linearly with h: 1.4e-2 at
+  h = 1e-6 down to 7.8e-5 at h = 1e-10, measured), so the oracle's adjoint is
+  the reference at that horizon;
 * the two scalar diagnostics the adjoint serves, through the autograd
   Function: field energy in a probe region plus a species' kinetic energy,
   against the oracle's adjoint with the analytic seeds (1e-9) and against
@@ -304,19 +309,128 @@ def test_autograd_matches_finite_differences_at_full_size():
     errs = []
     with torch.no_grad():
         h = 1e-6
-        for p, k in picks:
+
+        def central(p, k, hh):
             Pp = P0.clone()
-            Pp[p, k] += h
+            Pp[p, k] += hh
             Pm = P0.clone()
-            Pm[p, k] -= h
-            fd = (loss(a0, Pp, True) - loss(a0, Pm, True)).item() / (2 * h)
-            errs.append(abs(fd - gP[p, k]) / abs(fd))
+            Pm[p, k] -= hh
+            return (loss(a0, Pp, True) - loss(a0, Pm, True)).item() / (2 * hh)
+        rows = []
+        for p, k in picks:
+            # the central difference at h; its change between h and h/2
+            # measures its noise (the rounding of the loss, about 1e-14 for a
+            # field energy summed over 196,608 values, over 2h): a wrong
+            # adjoint would differ from both quotients alike
+            f1, f2 = central(p, k, h), central(p, k, 0.5 * h)
+            errs.append(abs(f1 - gP[p, k]) / abs(f1))
+            rows.append((abs(f1 - gP[p, k]), abs(f1 - f2), p, k, f1, f2, gP[p, k]))
     errs = np.array(errs)
-    log(f"  dL/d(u, x): median rel {np.median(errs):.2e}, max {errs.max():.2e}, "
-        f"{int(np.sum(errs > 1e-6))} of {len(errs)} above 1e-6")
-    assert np.mean(errs <= 1e-6) >= 0.95
-    assert errs.max() <= 1e-4
+    excess = np.array([r[0] - 1e-6 * abs(r[4]) - 2.0 * r[1] for r in rows])
+    for r in sorted(rows, key=lambda r: -r[0] / abs(r[4]))[:3]:
+        log(f"  largest relative error: particle {r[2]} comp {r[3]}: fd(h) {r[4]:.12e} "
+            f"fd(h/2) {r[5]:.12e} adjoint {r[6]:.12e}")
+    # which sampled components take another piece of the step within +-h:
+    # the particle's cells and stagger cells along its +h and -h trajectories
+    # (the oracle's push in the fields of the unperturbed run, step by step)
+    EBa = EB0(a0)
+    sim.set_fields([EBa[k].contiguous() for k in range(6)])
+    cols = [P0[:, k].contiguous() for k in range(6)]
+    sim.load_particles(0, *cols, torch.arange(sp.n, dtype=torch.int64, device=dev))
+    snaps = []
+    for _ in range(steps):
+        snaps.append([np.ascontiguousarray(f) for f in sim.fields()[:6]])
+        sim.step(1)
+    P0h = P0.cpu().numpy()
+    kinked = np.array([_kinked(wl, snaps, P0h[p], k, h) for p, k in picks])
+    ok = ~kinked
+    log(f"  dL/d(u, x): {int(kinked.sum())} of {len(errs)} components cross a kink within "
+        f"+-h; on the others relative error median {np.median(errs[ok]):.2e}, max "
+        f"{errs[ok].max():.2e}; {int(np.sum(errs[ok] > 1e-6))} above 1e-6, all within 1e-6 "
+        f"plus twice the quotient's change between h and h/2 (max excess {excess[ok].max():.2e})")
+    assert np.all(excess[ok] <= 0.0), excess[ok].max()
+    assert np.median(errs[ok]) <= 1e-7
+    assert kinked.sum() <= 12
     sim.close()
+
+
+def _kinked(wl, snaps, state, k, h):
+    """Whether component k of one particle's initial state, moved by +-h,
+    changes which cell or stagger cell the particle occupies at some step
+    (a kink of the piecewise-smooth map: a CIC weight or the set of VB
+    crossings changes its piece), following the particle with the oracle's
+    gather, Boris push, advance and wrap through the field snapshots of the
+    unperturbed run (the particle's own effect on the fields is left out)."""
+    sp = wl.species[0]
+    g = oracle.make_grid(wl.n, wl.dx, wl.dt, wl.S)
+
+    def pieces(sign):
+        x = np.array(state[0:3], dtype=np.float64)
+        u = np.array(state[3:6], dtype=np.float64)
+        (x if k < 3 else u)[k % 3] += sign * h
+        out = []
+        for F in snaps:
+            out.append((tuple(np.floor(x)), tuple(np.floor(x - 0.5))))
+            f = oracle.gather(g, F, x)
+            u = oracle.boris(sp.charge, sp.mass, wl.dt, f, u)
+            x = oracle.wrap(g, oracle.advance(g, u, x))
+        out.append((tuple(np.floor(x)), tuple(np.floor(x - 0.5))))
+        return out
+    return pieces(1.0) != pieces(-1.0)
+
+
+def test_400_steps_checkpoint_20_against_oracle_adjoint():
+    """The config-5 grid and schedule (32^3 cells, eight E_x modes, v_th 0.02,
+    400 steps, checkpoints every 20, re-sorts every 20, deterministic J) with
+    2 of its 16 particles per cell (65,536 electrons, weight scaled to keep
+    n0 = 1, so that the oracle's recorded run fits in a test): the gradient of
+    the final field energy with respect to the eight mode amplitudes, to the
+    initial fields and to every initial momentum equals the oracle's
+    recorded-run adjoint.  The oracle follows its own forward trajectory, which
+    differs from the GPU's by rounding grown over 400 steps (a 1e-13 change of
+    one momentum grows to about 1e-10 in the positions by step 400)."""
+    import math
+    wl = W.config5()
+    sp = wl.species[0]
+    keep = slice(0, sp.n, 8)
+    arrays = [np.ascontiguousarray(a[keep]) for a in sp.arrays()]
+    n = len(arrays[0])
+    w = sp.weight * 8.0
+    species = [(sp.charge, sp.mass, w)]
+    sim = pic.Simulation(wl.n, wl.dx, wl.dt, [(sp.charge, sp.mass, w, n)], supercell=wl.S,
+                         rebin_every=wl.R, deterministic_j=True)
+    sim.set_fields(wl.fields)
+    sim.load_particles(0, *arrays)
+    F0, P0 = _state(sim, 1)
+    sim.record(20)
+    sim.step(400)
+    F1, P1 = _state(sim, 1)
+    gF, gP = sim.backward([F1[c].copy() for c in range(6)], None)
+    sim.close()
+    log(f"  400 steps of {n} particles on the GPU; oracle recorded run")
+    o = _oracle_from(wl, species, F0, P0, wl.R)
+    tape = o.run_recorded(400)
+    del P1
+    oF, oP = o.adjoint(tape, [o.F[c].copy() for c in range(6)], None)
+    del tape
+    nx, ny, nz = wl.n
+    xi = np.arange(nx) + 0.5
+    ga, oa = [], []
+    for m in range(1, 9):
+        mode = np.tile(np.cos(2 * math.pi * m * xi / nx), ny * nz)
+        ga.append(float(gF[0] @ mode))
+        oa.append(float(oF[0] @ mode))
+    ga, oa = np.array(ga), np.array(oa)
+    ra = np.max(np.abs(ga - oa) / np.abs(oa))
+    rf = max(_rel(gF[c], oF[c]) for c in range(6))
+    ru = max(_rel(gP[0][k], oP[0][k]) for k in range(3, 6))
+    rx = max(_rel(gP[0][k], oP[0][k]) for k in range(3))
+    log(f"  400 steps: mode gradients rel {ra:.2e}, field gradients {rf:.2e}, momenta "
+        f"{ru:.2e}, positions {rx:.2e}")
+    assert ra <= 1e-8
+    assert rf <= 1e-8
+    assert ru <= 1e-8
+    assert rx <= 1e-8
 
 
 def test_autograd_probe_energy_and_kinetic_energy_losses():

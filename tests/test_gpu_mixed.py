@@ -212,22 +212,29 @@ def test_mixed_long_run_against_fp64_gpu():
             P = sim.particles(0)
             n = P["n"]
             mom = [float(np.sum(P[k][:n])) for k in ("ux", "uy", "uz")]
+            absmom = [float(np.sum(np.abs(P[k][:n]))) for k in ("ux", "uy", "uz")]
             # the mean charge density is n0 = 1, so the Gauss drift is
             # relative to the density scale
             out[prec] = dict(WE=d[0], WB=d[1], K=d[2], Q=d[3], gauss=d[4], divB=d[5], mom=mom,
-                             K0=d0[2])
+                             absmom=absmom, K0=d0[2])
         finally:
             sim.close()
     a, b = out["fp64"], out["mixed"]
     log(f"  200 steps, FP64: {a}")
     log(f"  200 steps, mixed: {b}")
+    rel = {k: abs(a[k] - b[k]) / abs(a[k]) for k in ("WE", "WB", "K")}
+    mom = [abs(a["mom"][d] - b["mom"][d]) / a["absmom"][d] for d in range(3)]
+    log(f"  mixed vs FP64 after 200 steps: relative {rel}, momentum / sum|u| {mom}")
     assert a["Q"] == b["Q"]
     assert a["gauss"] <= 1e-12
-    # FP32 rounding of J breaks exact continuity: a random walk of ~1e-7
-    # relative per step
-    assert b["gauss"] <= 1e-4
-    for key in ("WE", "K"):
-        assert abs(a[key] - b[key]) <= 1e-2 * abs(a[key]), key
+    # FP32 rounding of J breaks exact continuity: a random walk, observed
+    # 5.6e-8 of the density scale after 200 steps; bound 5e-6
+    assert b["gauss"] <= 5e-6
+    # observed about 1e-6 (W_E, W_B), 2e-8 (K) and 1e-8 of sum |u_d| (the
+    # summed momentum); bounds about 100 times larger
+    assert rel["WE"] <= 1e-4 and rel["WB"] <= 1e-4, rel
+    assert rel["K"] <= 1e-6, rel
+    assert max(mom) <= 1e-6, mom
 
 
 def test_precision_variant_full_size_128c_32ppc():
@@ -261,14 +268,28 @@ def test_precision_variant_full_size_128c_32ppc():
                 sim.load_particles(0, *[state[k] for k in keys[:6]], state["id"])
             sim.step(200)
             d = sim.diagnostics()
-            out[prec] = dict(WE=d[0], WB=d[1], K=d[2], Q=d[3], gauss=d[4])
+            end = {k: torch.empty(n, dtype=torch.int64 if k == "id" else torch.float64,
+                                  device=dev) for k in keys}
+            pic.pic_get_particles(sim.ctx, 0, capacity=n, out=end)
+            mom = [float(torch.sum(end[k])) for k in ("ux", "uy", "uz")]
+            absmom = [float(torch.sum(torch.abs(end[k]))) for k in ("ux", "uy", "uz")]
+            del end
+            out[prec] = dict(WE=d[0], WB=d[1], K=d[2], Q=d[3], gauss=d[4], mom=mom,
+                             absmom=absmom)
         finally:
             sim.close()
     a, b = out["fp64"], out["mixed"]
     log(f"  200 steps, FP64: {a}")
     log(f"  200 steps, mixed: {b}")
+    rel = {k: abs(a[k] - b[k]) / abs(a[k]) for k in ("WE", "WB", "K")}
+    mom = [abs(a["mom"][d] - b["mom"][d]) / a["absmom"][d] for d in range(3)]
+    log(f"  mixed vs FP64 after 200 steps: relative {rel}, momentum / sum|u| {mom}")
     assert a["Q"] == b["Q"]
     assert a["gauss"] <= 1e-11
-    assert b["gauss"] <= 1e-4
-    for key in ("WE", "K"):
-        assert abs(a[key] - b[key]) <= 1e-2 * abs(a[key]), key
+    # observed 4.4e-9 of the density scale; bound 5e-7
+    assert b["gauss"] <= 5e-7
+    # observed 1.2e-8 (W_E), 8.9e-8 (W_B), 1.1e-10 (K), about 2e-9 of
+    # sum |u_d| (momentum); bounds about 100 times larger
+    assert rel["WE"] <= 1e-6 and rel["WB"] <= 1e-5, rel
+    assert rel["K"] <= 1e-8, rel
+    assert max(mom) <= 2e-7, mom
