@@ -277,6 +277,19 @@ int pic_backward(pic_ctx* ctx, const double* const seed_fields[6],
 int pic_eval_sqrt_div(int64_t n, const double* x, const double* a, const double* b, double* sq,
                       double* dv);
 
+/* pic_eval_sqrt_div for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results, bit for bit, with the arrays staged through a
+ * fixed 8 MiB device buffer that the library holds on each device it runs on
+ * until the process ends, instead of buffers allocated per call.  The call
+ * makes no hipMalloc / hipFree (the buffer's address is looked up once per
+ * device, on the first call with that device current).  n is limited to
+ * 209,696 (five arrays of n doubles in 8 MiB): larger n gives PIC_EINVAL with
+ * a message (pic_last_error(NULL)).  Calls that overlap on one device share
+ * the buffer and race; each call overwrites what it reads. */
+int pic_eval_sqrt_div_noalloc(int64_t n, const double* x, const double* a, const double* b,
+                              double* sq, double* dv);
+
 /* Message of the last failure on ctx (or of the last failed pic_create or
  * context-free call when ctx is NULL).  Owned by the library; valid until the
  * next call. */

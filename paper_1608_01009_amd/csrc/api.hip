@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -700,6 +701,84 @@ int pic_eval_sqrt_div(int64_t n, const double* x, const double* a, const double*
     if (want_dv && (e = hipMemcpy(dv, d[4], bytes, hipMemcpyDefault)) != hipSuccess)
         return hfail(e, "hipMemcpy");
     release();
+    return PIC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Staging of pic_eval_sqrt_div_noalloc: one array per device, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress (per device, on the first call made
+// with that device current) and only that address is used.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+}  // namespace
+
+extern "C" {
+
+int pic_eval_sqrt_div_noalloc(int64_t n, const double* x, const double* a, const double* b,
+                              double* sq, double* dv) {
+    g_create_error.clear();
+    const bool want_sq = x != nullptr || sq != nullptr;
+    const bool want_dv = a != nullptr || b != nullptr || dv != nullptr;
+    if (n < 0 || (want_sq && (!x || !sq)) || (want_dv && (!a || !b || !dv))) {
+        g_create_error = "pic_eval_sqrt_div_noalloc: n must be >= 0 and x/sq, a/b/dv given together";
+        return PIC_EINVAL;
+    }
+    // five arrays of n doubles, each starting on a 256-byte boundary
+    const size_t slot_max = (kNoAllocScratchBytes / 5) & ~(size_t)255;
+    const int64_t n_max = (int64_t)(slot_max / sizeof(double));
+    const size_t slot = (((size_t)(n > 0 ? n : 0) * sizeof(double)) + 255) & ~(size_t)255;
+    if (n > n_max) {
+        g_create_error = "pic_eval_sqrt_div_noalloc: n exceeds " + std::to_string(n_max) +
+                         " (the staging holds five arrays in " +
+                         std::to_string(kNoAllocScratchBytes >> 20) + " MiB)";
+        return PIC_EINVAL;
+    }
+    if (n == 0 || (!want_sq && !want_dv)) return PIC_OK;
+    auto hfail = [&](hipError_t e, const char* what) {
+        g_create_error = std::string("pic_eval_sqrt_div_noalloc: ") + what + ": " +
+                         hipGetErrorString(e);
+        return PIC_EDEVICE;
+    };
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hfail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return hfail(hipErrorInvalidDevice, "device index");
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) return hfail(e, "hipGetSymbolAddress");
+            g_scratch_ptr[dev] = ptr;
+        }
+        base = (unsigned char*)g_scratch_ptr[dev];
+    }
+    double* d[5];
+    for (int k = 0; k < 5; ++k) d[k] = (double*)(base + (size_t)k * slot);
+    const size_t bytes = (size_t)n * sizeof(double);
+    const double* in[3] = {x, a, b};
+    const bool use_in[3] = {want_sq, want_dv, want_dv};
+    for (int k = 0; k < 3; ++k)
+        if (use_in[k] && (e = hipMemcpy(d[k], in[k], bytes, hipMemcpyDefault)) != hipSuccess)
+            return hfail(e, "hipMemcpy");
+    e = launch_sqrt_div(n, want_sq ? d[0] : nullptr, want_dv ? d[1] : nullptr,
+                        want_dv ? d[2] : nullptr, want_sq ? d[3] : nullptr,
+                        want_dv ? d[4] : nullptr, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hfail(e, "kernel");
+    if (want_sq && (e = hipMemcpy(sq, d[3], bytes, hipMemcpyDefault)) != hipSuccess)
+        return hfail(e, "hipMemcpy");
+    if (want_dv && (e = hipMemcpy(dv, d[4], bytes, hipMemcpyDefault)) != hipSuccess)
+        return hfail(e, "hipMemcpy");
     return PIC_OK;
 }
 

@@ -41,7 +41,8 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
 ABI_SYMBOLS = ("pic_create", "pic_load_particles", "pic_set_fields", "pic_step",
                "pic_get_fields", "pic_get_particles", "pic_diagnostics", "pic_enable_timers",
                "pic_get_timers", "pic_get_counters", "pic_record", "pic_backward", "pic_set_laser",
-               "pic_eval_sqrt_div", "pic_last_error", "pic_destroy")
+               "pic_eval_sqrt_div", "pic_eval_sqrt_div_noalloc", "pic_last_error",
+               "pic_destroy")
 
 
 class PicGrid(C.Structure):
@@ -98,6 +99,7 @@ def library():
         L.pic_set_laser.argtypes = [V, C.c_double, C.c_double, C.c_double, C.c_int32]
         L.pic_backward.argtypes = [V, C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V)]
         L.pic_eval_sqrt_div.argtypes = [C.c_int64, V, V, V, V, V]
+        L.pic_eval_sqrt_div_noalloc.argtypes = [C.c_int64, V, V, V, V, V]
         L.pic_last_error.argtypes = [V]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [V]
@@ -287,10 +289,12 @@ def pic_backward(ctx, ncell: int, counts: Sequence[int], seed_fields=None, seed_
     return grad_fields, grad_particles
 
 
-def pic_eval_sqrt_div(x=None, a=None, b=None):
+def pic_eval_sqrt_div(x=None, a=None, b=None, noalloc=False):
     """The push's square root of x (>= 1) and quotient a / b (1 <= b < 2^1000)
     evaluated by the library (host or device arrays of equal length); returns
-    (sqrt, quotient) as new arrays of the inputs' kind, None where not asked."""
+    (sqrt, quotient) as new arrays of the inputs' kind, None where not asked.
+    noalloc: through pic_eval_sqrt_div_noalloc (no device allocation in the
+    library; n at most 209,696)."""
     n = len(x) if x is not None else len(a)
     like = x if x is not None else a
 
@@ -301,7 +305,8 @@ def pic_eval_sqrt_div(x=None, a=None, b=None):
         return np.empty(n, dtype=np.float64)
     sq = new() if x is not None else None
     dv = new() if a is not None else None
-    _check(None, library().pic_eval_sqrt_div(
+    fn = library().pic_eval_sqrt_div_noalloc if noalloc else library().pic_eval_sqrt_div
+    _check(None, fn(
         n, _addr(x, n, np.float64), _addr(a, n, np.float64), _addr(b, n, np.float64),
         _addr(sq, n, np.float64), _addr(dv, n, np.float64)))
     return sq, dv
