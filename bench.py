@@ -128,9 +128,24 @@ def copy_bandwidth(mib: int = 1024, reps: int = 10):
             "method": f"torch copy_ of a {mib} MiB FP64 tensor, HIP events, {reps} repeats"}
 
 
-def cpu_baseline(wl, steps: int):
-    """The oracle as it stands (single-threaded C, FP64) on the host: `steps`
-    full steps of the same workload."""
+def host_cpu():
+    """Model name and core counts of the host the benchmark runs on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "cpu_count": os.cpu_count(), "usable_cpus": usable}
+
+
+def _oracle_rate(wl, steps: int):
     import oracle
     o = oracle.OracleSim(wl.n, wl.dx, wl.dt, [(s.charge, s.mass, s.weight) for s in wl.species],
                          S=wl.S, R=wl.R)
@@ -140,10 +155,25 @@ def cpu_baseline(wl, steps: int):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    return wl.nparticles * steps / dt, dt
+
+
+def cpu_baseline(wl, steps: int):
+    """The oracle as it stands (single-threaded C, FP64) on the host: `steps`
+    full steps of the benchmark's workload (the reported value), and the
+    16^3 x 8 ppc workload run in full (100 steps) next to it."""
+    from paper_1608_01009_amd import workloads as W
+    rate, dt = _oracle_rate(wl, steps)
+    c1 = W.config1()
+    rate1, dt1 = _oracle_rate(c1, c1.steps)
     n = wl.nparticles
-    return {"value": n * steps / dt, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
+    return {"value": rate, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} full steps of the same workload ({n} particles, {wl.n[0]}^3 "
-                      f"cells), single-threaded C oracle, {dt:.2f} s"}
+                      f"cells), single-threaded C oracle, {dt:.2f} s",
+            "host": host_cpu(),
+            "uniform_16c_8ppc_full_run": {"particles": c1.nparticles, "steps": c1.steps,
+                                          "seconds": dt1, "value": rate1,
+                                          "unit": "particle updates/s", "cores": 1}}
 
 
 def mixed_leg(wl, args):
@@ -315,7 +345,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-mixed leg (same workload, PIC_FP32_MIXED)")

@@ -277,6 +277,15 @@ int pic_backward(pic_ctx* ctx, const double* const seed_fields[6],
 int pic_eval_sqrt_div(int64_t n, const double* x, const double* a, const double* b, double* sq,
                       double* dv);
 
+/* The FP32 counterparts used by the PIC_FP32_MIXED push, for comparison with
+ * any correctly rounded FP32 reference: sq[i] = sqrt(x[i]) for finite
+ * x[i] >= 1; dv[i] = a[i] / b[i] for 1 <= b[i] < 2^64 and a[i] = 0 or
+ * 2^-60 < |a[i]| < 2^60 (the push divides h, 2 and 1 by values >= 1;
+ * pic_create checks |h| for mixed-precision contexts).  Arrays of n floats,
+ * otherwise as pic_eval_sqrt_div. */
+int pic_eval_sqrt_div_f32(int64_t n, const float* x, const float* a, const float* b, float* sq,
+                          float* dv);
+
 /* pic_eval_sqrt_div for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same results, bit for bit, with the arrays staged through a

@@ -704,6 +704,50 @@ int pic_eval_sqrt_div(int64_t n, const double* x, const double* a, const double*
     return PIC_OK;
 }
 
+int pic_eval_sqrt_div_f32(int64_t n, const float* x, const float* a, const float* b, float* sq,
+                          float* dv) {
+    g_create_error.clear();
+    const bool want_sq = x != nullptr || sq != nullptr;
+    const bool want_dv = a != nullptr || b != nullptr || dv != nullptr;
+    if (n < 0 || (want_sq && (!x || !sq)) || (want_dv && (!a || !b || !dv))) {
+        g_create_error = "pic_eval_sqrt_div_f32: n must be >= 0 and x/sq, a/b/dv given together";
+        return PIC_EINVAL;
+    }
+    if (n == 0 || (!want_sq && !want_dv)) return PIC_OK;
+    const size_t bytes = (size_t)n * sizeof(float);
+    float* d[5] = {};
+    auto release = [&]() {
+        for (float* p : d)
+            if (p) (void)hipFree(p);
+    };
+    auto hfail = [&](hipError_t e, const char* what) {
+        g_create_error = std::string("pic_eval_sqrt_div_f32: ") + what + ": " +
+                         hipGetErrorString(e);
+        release();
+        return e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE;
+    };
+    const float* in[3] = {x, a, b};
+    const bool use[5] = {want_sq, want_dv, want_dv, want_sq, want_dv};
+    for (int k = 0; k < 5; ++k) {
+        if (!use[k]) continue;
+        hipError_t e = hipMalloc((void**)&d[k], bytes);
+        if (e != hipSuccess) return hfail(e, "hipMalloc");
+        if (k < 3) {
+            e = hipMemcpy(d[k], in[k], bytes, hipMemcpyDefault);
+            if (e != hipSuccess) return hfail(e, "hipMemcpy");
+        }
+    }
+    hipError_t e = launch_sqrt_div_f32(n, d[0], d[1], d[2], d[3], d[4], nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hfail(e, "kernel");
+    if (want_sq && (e = hipMemcpy(sq, d[3], bytes, hipMemcpyDefault)) != hipSuccess)
+        return hfail(e, "hipMemcpy");
+    if (want_dv && (e = hipMemcpy(dv, d[4], bytes, hipMemcpyDefault)) != hipSuccess)
+        return hfail(e, "hipMemcpy");
+    release();
+    return PIC_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -841,6 +885,11 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         const double hq = std::fabs((q.charge * dt) / (2.0 * q.mass));
         if (hq != 0.0 && !(hq > 0x1p-900 && hq < 0x1p900))
             return bad("|charge dt / (2 mass)| must be 0 or within (2^-900, 2^900)");
+        // the FP32 push divides (float) h by values >= 1
+        const double hf = std::fabs((double)(float)((q.charge * dt) / (2.0 * q.mass)));
+        if (grid->precision == PIC_FP32_MIXED && hf != 0.0 && !(hf > 0x1p-60 && hf < 0x1p60))
+            return bad("mixed precision: |charge dt / (2 mass)| must be 0 or within "
+                       "(2^-60, 2^60) in FP32");
     }
 
     pic_ctx* c = new (std::nothrow) pic_ctx();

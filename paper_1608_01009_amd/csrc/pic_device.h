@@ -80,6 +80,34 @@ __device__ __forceinline__ double div_ge1(double a, double b) {
     return __fma_rn(e, r, q);
 }
 
+// FP32 square root of x >= 1 (finite), correctly rounded: the hardware
+// square root (within one unit in the last place) moved to the neighbour
+// above or below when the fused residual against it has the right sign.
+// These are the operations of the general IEEE FP32 square root of gfx9 less
+// its scaling of tiny operands and its special-value select, neither of which
+// acts for x >= 1, so the result is the same bit for bit.
+__device__ __forceinline__ float sqrt_ge1_f32(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float dn = __int_as_float(__float_as_int(s) - 1);
+    const float up = __int_as_float(__float_as_int(s) + 1);
+    float r = __fmaf_rn(-dn, s, x) <= 0.0f ? dn : s;
+    r = __fmaf_rn(-up, s, x) > 0.0f ? up : r;
+    return r;
+}
+
+// FP32 a / b, correctly rounded, for 1 <= b < 2^64 and a = 0 or
+// 2^-60 < |a| < 2^60: reciprocal estimate, one Newton step, quotient and two
+// fused residual corrections; the operations of the general IEEE FP32
+// division of gfx9 less its operand scaling and special-case fix-up, which do
+// not act for quotients in the normal range.
+__device__ __forceinline__ float div_ge1_f32(float a, float b) {
+    float r = __builtin_amdgcn_rcpf(b);
+    r = __fmaf_rn(__fmaf_rn(-b, r, 1.0f), r, r);
+    float q = a * r;
+    q = __fmaf_rn(__fmaf_rn(-b, q, a), r, q);
+    return __fmaf_rn(__fmaf_rn(-b, q, a), r, q);
+}
+
 __device__ __forceinline__ double one_plus_sq(const double v[3]) {
     return __fma_rn(v[2], v[2], __fma_rn(v[1], v[1], __fma_rn(v[0], v[0], 1.0)));
 }

@@ -225,6 +225,11 @@ hipError_t launch_unpermute(int64_t n, const unsigned* perm, double* const src[6
 // [1, 2^1000)) on device arrays; sq or dv NULL skips that part.
 hipError_t launch_sqrt_div(int64_t n, const double* x, const double* a, const double* b,
                            double* sq, double* dv, hipStream_t s);
+// The same for the mixed-precision push's FP32 square root (x >= 1) and
+// division (divisor in [1, 2^64), numerator 0 or of magnitude in
+// (2^-60, 2^60)).
+hipError_t launch_sqrt_div_f32(int64_t n, const float* x, const float* a, const float* b,
+                               float* sq, float* dv, hipStream_t s);
 
 // Diagnostics.
 hipError_t launch_sum_squares(const double* const a[3], int64_t n, double* acc, hipStream_t s);

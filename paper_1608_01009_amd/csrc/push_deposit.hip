@@ -945,13 +945,20 @@ hipError_t launch_push_deposit_pair(const Geom& g, const SpeciesC* sp, const Par
 
 namespace {
 
-// The push's square root and division on arrays (the library's self-check).
-__global__ void __launch_bounds__(256) sqrt_div_kernel(int64_t n, const double* x, const double* a,
-                                                      const double* b, double* sq, double* dv) {
+// The push's square root and division on arrays (the library's self-check),
+// FP64 or (mixed-precision push) FP32.
+template <class F>
+__global__ void __launch_bounds__(256) sqrt_div_kernel(int64_t n, const F* x, const F* a,
+                                                      const F* b, F* sq, F* dv) {
     for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * 256) {
-        if (sq) sq[i] = sqrt_ge1(x[i]);
-        if (dv) dv[i] = div_ge1(a[i], b[i]);
+        if constexpr (sizeof(F) == 8) {
+            if (sq) sq[i] = sqrt_ge1(x[i]);
+            if (dv) dv[i] = div_ge1(a[i], b[i]);
+        } else {
+            if (sq) sq[i] = sqrt_ge1_f32(x[i]);
+            if (dv) dv[i] = div_ge1_f32(a[i], b[i]);
+        }
     }
 }
 
@@ -962,7 +969,18 @@ hipError_t launch_sqrt_div(int64_t n, const double* x, const double* a, const do
     if (n <= 0) return hipSuccess;
     int64_t nb = (n + 255) / 256;
     if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(sqrt_div_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, x, a, b, sq, dv);
+    hipLaunchKernelGGL(sqrt_div_kernel<double>, dim3((unsigned)nb), dim3(256), 0, s, n, x, a, b,
+                       sq, dv);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqrt_div_f32(int64_t n, const float* x, const float* a, const float* b,
+                               float* sq, float* dv, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(sqrt_div_kernel<float>, dim3((unsigned)nb), dim3(256), 0, s, n, x, a, b,
+                       sq, dv);
     return hipGetLastError();
 }
 

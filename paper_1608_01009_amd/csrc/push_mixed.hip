@@ -15,6 +15,7 @@
 // contraction off elsewhere, correctly rounded square roots and divisions),
 // so cells, offsets and momenta are reproducible bit for bit by any IEEE FP32
 // evaluation of the same expressions.
+#include "pic_device.h"
 #include "pic_internal.h"
 
 namespace pic {
@@ -23,11 +24,6 @@ namespace {
 constexpr int kBlock = 512;
 constexpr int kCellBits = 10;
 constexpr unsigned kCellMask = (1u << kCellBits) - 1u;
-
-__device__ __forceinline__ int wrapi(int i, int n) {
-    int r = i % n;
-    return r < 0 ? r + n : r;
-}
 
 __device__ __forceinline__ int near_wrap(int i, int n) {
     i = i < 0 ? i + n : i;
@@ -210,6 +206,9 @@ __device__ __forceinline__ float add_crossf(const float a[3], const float b[3], 
 }
 
 // Boris rotation and the cell-local advance o1 = fma((dt/dx_d) u_d, g, o).
+// The square roots (of values >= 1) and divisions (by values >= 1, of h, 2
+// and 1; |h| is range-checked when a context is created) are correctly
+// rounded.
 __device__ __forceinline__ void boris_advance_m(const SpeciesM& sp, const float E[3],
                                                 const float B[3], float u[3], const float o[3],
                                                 float o1[3]) {
@@ -218,10 +217,10 @@ __device__ __forceinline__ void boris_advance_m(const SpeciesM& sp, const float 
     float um[3], t[3], s[3], up[3], upl[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) um[d] = __fmaf_rn(h, E[d], u[d]);
-    const float hg = h / sqrtf(one_plus_sqf(um));
+    const float hg = div_ge1_f32(h, sqrt_ge1_f32(one_plus_sqf(um)));
 #pragma unroll
     for (int d = 0; d < 3; ++d) t[d] = hg * B[d];
-    const float sf = 2.0f / one_plus_sqf(t);
+    const float sf = div_ge1_f32(2.0f, one_plus_sqf(t));
 #pragma unroll
     for (int d = 0; d < 3; ++d) s[d] = sf * t[d];
 #pragma unroll
@@ -230,7 +229,7 @@ __device__ __forceinline__ void boris_advance_m(const SpeciesM& sp, const float 
     for (int d = 0; d < 3; ++d) upl[d] = add_crossf(um, up, s, d);
 #pragma unroll
     for (int d = 0; d < 3; ++d) u[d] = __fmaf_rn(h, E[d], upl[d]);
-    const float gi = 1.0f / sqrtf(one_plus_sqf(u));
+    const float gi = div_ge1_f32(1.0f, sqrt_ge1_f32(one_plus_sqf(u)));
 #pragma unroll
     for (int d = 0; d < 3; ++d) o1[d] = __fmaf_rn(sp.cdt[d] * u[d], gi, o[d]);
 }

@@ -41,8 +41,8 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVIC
 ABI_SYMBOLS = ("pic_create", "pic_load_particles", "pic_set_fields", "pic_step",
                "pic_get_fields", "pic_get_particles", "pic_diagnostics", "pic_enable_timers",
                "pic_get_timers", "pic_get_counters", "pic_record", "pic_backward", "pic_set_laser",
-               "pic_eval_sqrt_div", "pic_eval_sqrt_div_noalloc", "pic_last_error",
-               "pic_destroy")
+               "pic_eval_sqrt_div", "pic_eval_sqrt_div_f32", "pic_eval_sqrt_div_noalloc",
+               "pic_last_error", "pic_destroy")
 
 
 class PicGrid(C.Structure):
@@ -100,6 +100,7 @@ def library():
         L.pic_backward.argtypes = [V, C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V)]
         L.pic_eval_sqrt_div.argtypes = [C.c_int64, V, V, V, V, V]
         L.pic_eval_sqrt_div_noalloc.argtypes = [C.c_int64, V, V, V, V, V]
+        L.pic_eval_sqrt_div_f32.argtypes = [C.c_int64, V, V, V, V, V]
         L.pic_last_error.argtypes = [V]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [V]
@@ -289,26 +290,45 @@ def pic_backward(ctx, ncell: int, counts: Sequence[int], seed_fields=None, seed_
     return grad_fields, grad_particles
 
 
-def pic_eval_sqrt_div(x=None, a=None, b=None, noalloc=False):
+def pic_eval_sqrt_div(x=None, a=None, b=None, noalloc=False, f32=False):
     """The push's square root of x (>= 1) and quotient a / b (1 <= b < 2^1000)
     evaluated by the library (host or device arrays of equal length); returns
     (sqrt, quotient) as new arrays of the inputs' kind, None where not asked.
     noalloc: through pic_eval_sqrt_div_noalloc (no device allocation in the
-    library; n at most 209,696)."""
+    library; n at most 209,696).  f32: the mixed-precision push's FP32
+    versions (float32 arrays; pic_eval_sqrt_div_f32)."""
     n = len(x) if x is not None else len(a)
     like = x if x is not None else a
+    dt = np.float32 if f32 else np.float64
 
     def new():
         if _is_torch(like):
             import torch
-            return torch.empty(n, dtype=torch.float64, device=like.device)
-        return np.empty(n, dtype=np.float64)
+            return torch.empty(n, dtype=torch.float32 if f32 else torch.float64,
+                               device=like.device)
+        return np.empty(n, dtype=dt)
+
+    def addr(v):
+        if v is None:
+            return None
+        if _is_torch(v):
+            import torch
+            want = torch.float32 if f32 else torch.float64
+            if v.dtype != want or not v.is_contiguous() or v.numel() < n:
+                raise ValueError(f"tensor must be contiguous {want} with >= {n} elements")
+            return v.data_ptr()
+        if not isinstance(v, np.ndarray) or v.dtype != dt or not v.flags.c_contiguous or v.size < n:
+            raise ValueError(f"array must be a contiguous {np.dtype(dt)} ndarray with >= {n} "
+                             f"elements")
+        return v.ctypes.data
     sq = new() if x is not None else None
     dv = new() if a is not None else None
-    fn = library().pic_eval_sqrt_div_noalloc if noalloc else library().pic_eval_sqrt_div
-    _check(None, fn(
-        n, _addr(x, n, np.float64), _addr(a, n, np.float64), _addr(b, n, np.float64),
-        _addr(sq, n, np.float64), _addr(dv, n, np.float64)))
+    L = library()
+    fn = L.pic_eval_sqrt_div_f32 if f32 else (L.pic_eval_sqrt_div_noalloc if noalloc
+                                              else L.pic_eval_sqrt_div)
+    if f32 and noalloc:
+        raise ValueError("the no-allocation variant is FP64 only")
+    _check(None, fn(n, addr(x), addr(a), addr(b), addr(sq), addr(dv)))
     return sq, dv
 
 

@@ -68,3 +68,37 @@ def test_sqrt_and_div_bit_exact():
     assert bad_sq.size == 0, (bad_sq.size, x[bad_sq[:5]], sq[bad_sq[:5]], ref_sq[bad_sq[:5]])
     assert bad_dv.size == 0, (bad_dv.size, a[bad_dv[:5]], b[bad_dv[:5]], dv[bad_dv[:5]])
     print(f"sqrt and division bit for bit on {m} operands each")
+
+
+def test_f32_sqrt_and_div_bit_exact():
+    """The FP32 versions used by the mixed-precision push, against numpy's
+    IEEE float32 square root and division: 2^24 random operands over their
+    ranges (x in [1, 2^60], b in [1, 2^63], |a| in [2^-60, 2^60]) plus 2^21
+    near-midpoint ones each (midpoints of two floats are exact in float64)."""
+    n = 1 << 24
+    x = np.exp2(RNG.uniform(0.0, 60.0, n)).astype(np.float32)
+    y = np.exp2(RNG.uniform(0.0, 30.0, 1 << 21)).astype(np.float32)
+    m = (y.astype(np.float64) + np.nextafter(y, np.float32(np.inf)).astype(np.float64)) / 2
+    xh = (m * m).astype(np.float32)
+    x = np.concatenate([x, xh[xh >= 1.0], np.arange(1, 4097, dtype=np.float32) ** 2,
+                        np.array([1.0, 2.0, 4.0, 2.0 ** 60], dtype=np.float32)])
+    a = (np.exp2(RNG.uniform(-60.0, 60.0, n)) *
+         np.where(RNG.random(n) < 0.5, -1.0, 1.0)).astype(np.float32)
+    b = np.exp2(RNG.uniform(0.0, 63.0, n)).astype(np.float32)
+    q = np.exp2(RNG.uniform(-30.0, 30.0, 1 << 21)).astype(np.float32)
+    qm = (q.astype(np.float64) + np.nextafter(q, np.float32(np.inf)).astype(np.float64)) / 2
+    bh = np.exp2(RNG.uniform(0.0, 25.0, 1 << 21)).astype(np.float32)
+    ah = (qm * bh.astype(np.float64)).astype(np.float32)
+    a = np.concatenate([a, ah, np.array([0.0, 1.0, 2.0, -1.0], dtype=np.float32)])
+    b = np.concatenate([b, bh, np.array([1.0, 3.0, 1.5, 2.0 ** 62], dtype=np.float32)])
+    mlen = min(len(x), len(a))
+    x, a, b = x[:mlen], a[:mlen], b[:mlen]
+    sq, dv = pic.pic_eval_sqrt_div(x, a, b, f32=True)
+    ref_sq = np.sqrt(x)
+    ref_dv = a / b
+    assert ref_sq.dtype == np.float32 and ref_dv.dtype == np.float32
+    bad_sq = np.flatnonzero(sq.view(np.int32) != ref_sq.view(np.int32))
+    bad_dv = np.flatnonzero(dv.view(np.int32) != ref_dv.view(np.int32))
+    assert bad_sq.size == 0, (bad_sq.size, x[bad_sq[:5]], sq[bad_sq[:5]], ref_sq[bad_sq[:5]])
+    assert bad_dv.size == 0, (bad_dv.size, a[bad_dv[:5]], b[bad_dv[:5]], dv[bad_dv[:5]])
+    print(f"FP32 sqrt and division bit for bit on {mlen} operands each")
