@@ -39,11 +39,14 @@ struct SpeciesState {
     unsigned* keys = nullptr;  // sort keys written by the push before a re-sort
     unsigned* perm = nullptr;  // re-sort order: new index -> index in buf[cur]
     bool pending = false;      // buf[cur] is still in the old order; apply perm
+    bool moved = false;        // the re-sort ending this step moved the data (perm valid)
     bool loaded = false;
 };
 
-// Mean particles per supercell from which a pending re-sort order is applied
-// by the staged permutation rather than read through by the push.
+// Mean particles per supercell from which a re-sort also moves the particle
+// data into the new order (the neighbourhood re-sort's staged move, or after
+// the global sort the staged permutation) rather than leaving the order for
+// the next push to read through.
 constexpr int64_t kStagedPermuteMin = 1024;
 
 enum Stage { ST_PUSH = 0, ST_PUSH_PERM = 1, ST_FAR = 2, ST_FDTD = 3, ST_SORT = 4, ST_TOTAL = 5,
@@ -250,6 +253,8 @@ int sync_and_check(pic_ctx* c, bool stepping) {
     if (e & ERR_BADPOS)
         return fail(c, stepping ? PIC_ENONFINITE : PIC_EINVAL,
                     "particle positions must be finite and inside [0, n) with finite momenta");
+    if (e & ERR_SORT)
+        return fail(c, PIC_EDEVICE, "internal error: inconsistent counts in the re-sort");
     return PIC_OK;
 }
 
@@ -283,13 +288,61 @@ int compute_refs(pic_ctx* c) {
     return PIC_OK;
 }
 
+// The arrays of a species from its current buffer to the other one.
+MoveArrays move_arrays(const pic_ctx* c, const SpeciesState& s) {
+    MoveArrays mv;
+    if (c->precision == PIC_FP64) {
+        const Parts& a = s.buf[s.cur];
+        const Parts& b = s.buf[1 - s.cur];
+        const void* src[7] = {a.x, a.y, a.z, a.ux, a.uy, a.uz, a.id};
+        void* dst[7] = {b.x, b.y, b.z, b.ux, b.uy, b.uz, b.id};
+        for (int k = 0; k < 7; ++k) {
+            mv.src[k] = src[k];
+            mv.dst[k] = dst[k];
+            mv.bytes[k] = 8;
+        }
+        mv.count = 7;
+    } else {
+        const PartsM& a = s.bufm[s.cur];
+        const PartsM& b = s.bufm[1 - s.cur];
+        const void* src[8] = {a.cell, a.ox, a.oy, a.oz, a.ux, a.uy, a.uz, a.id};
+        void* dst[8] = {b.cell, b.ox, b.oy, b.oz, b.ux, b.uy, b.uz, b.id};
+        for (int k = 0; k < 8; ++k) {
+            mv.src[k] = src[k];
+            mv.dst[k] = dst[k];
+            mv.bytes[k] = k < 7 ? 4 : 8;
+        }
+        mv.count = 8;
+    }
+    return mv;
+}
+
 // Order of the next re-sort from the keys written by the last push (or from
-// the positions when keys == nullptr); the data move with the next push.
-int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys) {
+// the positions when keys == nullptr).  after_push: keys come from the push of
+// the step that ends now, and the current order is grouped by the supercells
+// of sc_off, so the neighbourhood re-sort applies (unless a particle moved
+// farther than the neighbouring supercells); with dense supercells it also
+// moves the data into the new order.  Otherwise (a load, or the global sort)
+// the data move later: with the next push, or by the staged permutation.
+int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys, bool after_push) {
     HIPCHK(c, hipMemcpyAsync(s.sc_prev, s.sc_off, (size_t)(c->g.nsc + 1) * sizeof(int),
                              hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, launch_sort(c->g, s.n, keys, s.buf[s.cur], s.perm, s.sc_off, c->scratch, c->d_err,
-                          c->stream));
+    bool done = false;
+    const bool local = after_push && keys && !c->g.absorb_x;
+    const bool move = local && s.n >= (int64_t)kStagedPermuteMin * c->g.nsc;
+    const MoveArrays mv = move_arrays(c, s);
+    if (local)
+        HIPCHK(c, launch_sort_local(c->g, s.n, keys, s.sc_prev, s.perm, s.sc_off, c->scratch,
+                                    c->d_err, move ? &mv : nullptr, c->stream, &done));
+    if (done && move) {
+        s.cur = 1 - s.cur;
+        s.pending = false;
+        s.moved = true;
+        return PIC_OK;
+    }
+    if (!done)
+        HIPCHK(c, launch_sort(c->g, s.n, keys, s.buf[s.cur], s.perm, s.sc_off, c->scratch,
+                              c->d_err, c->stream));
     s.pending = true;
     if (c->g.absorb_x && s.n > 0) {
         // removed particles were sorted after every supercell: the species
@@ -318,6 +371,7 @@ int resolve_pending(pic_ctx* c, SpeciesState& s) {
 // One step of every species and the Yee update, queued on the stream
 // (no synchronisation); the re-sort order follows every R-th step.
 int step_once(pic_ctx* c) {
+    for (auto& s : c->sp) s.moved = false;
     const Fields f{{c->E[0], c->E[1], c->E[2]}, {c->B[0], c->B[1], c->B[2]}};
     const Fields fo{{c->Eo[0], c->Eo[1], c->Eo[2]}, {c->Bo[0], c->Bo[1], c->Bo[2]}};
     double* const* Jd = c->J[c->jdep];
@@ -377,14 +431,15 @@ int step_once(pic_ctx* c) {
         if (pair) break;
         if (s.n == 0) continue;
         const bool mixed = c->precision == PIC_FP32_MIXED;
-        if (s.pending && !mixed && !c->g.absorb_x && s.n >= (int64_t)kStagedPermuteMin * c->g.nsc) {
-            // dense supercells: the re-sort order is applied by a permutation
-            // staged through LDS, and the push reads in stored order (reading
-            // through the order instead touches about twelve times the cache
-            // lines per load when a supercell holds thousands of particles)
+        if (s.pending && !c->g.absorb_x && s.n >= (int64_t)kStagedPermuteMin * c->g.nsc) {
+            // dense supercells after the global sort: the re-sort order is
+            // applied by a permutation staged through LDS, and the push reads
+            // in stored order (reading through the order instead touches
+            // about twelve times the cache lines per load when a supercell
+            // holds thousands of particles)
             Timed t(c, ST_SORT);
-            HIPCHK(c, launch_staged_permute(c->g, s.n, s.perm, s.sc_prev, s.sc_off, s.buf[s.cur],
-                                            s.buf[1 - s.cur], c->stream));
+            HIPCHK(c, launch_staged_permute(c->g, s.n, s.perm, s.sc_prev, s.sc_off,
+                                            move_arrays(c, s), c->stream));
             s.cur = 1 - s.cur;
             s.pending = false;
         }
@@ -462,7 +517,7 @@ int step_once(pic_ctx* c) {
         Timed t(c, ST_SORT);
         for (auto& s : c->sp) {
             if (s.n == 0) continue;
-            int r = do_sort(c, s, s.keys);
+            int r = do_sort(c, s, s.keys, true);
             if (r != PIC_OK) return r;
         }
         c->steps_since_sort = 0;
@@ -622,8 +677,8 @@ int backward_sweep(pic_ctx* c, double* const lEB[6], std::vector<std::array<doub
             if (r != PIC_OK) return r;
             for (size_t si = 0; si < ns; ++si) {
                 SpeciesState& s = c->sp[si];
-                sorted[j][si] = s.pending ? 1 : 0;
-                if (!s.pending) continue;
+                sorted[j][si] = (s.pending || s.moved) ? 1 : 0;
+                if (!sorted[j][si]) continue;
                 HIPCHK(c, hipMemcpyAsync(stPerm[j][si], s.perm, (size_t)s.n * sizeof(unsigned),
                                          hipMemcpyDeviceToDevice, c->stream));
                 r = resolve_pending(c, s);
@@ -1113,7 +1168,7 @@ int pic_load_particles(pic_ctx* c, int32_t species, int64_t n, const double* x, 
     s.pending = false;
     {
         Timed t(c, ST_SORT);
-        int r = do_sort(c, s, mixed ? s.keys : nullptr);
+        int r = do_sort(c, s, mixed ? s.keys : nullptr, false);
         if (r == PIC_OK) r = resolve_pending(c, s);
         if (r != PIC_OK) return r;
     }

@@ -13,6 +13,7 @@ enum : unsigned {
     ERR_NONFINITE = 1u,   // a particle state became NaN / Inf during a step
     ERR_BADPOS = 2u,      // a loaded position is outside [0, n) or not finite
     ERR_DETCAP = 4u,      // deterministic J: a supercell holds more than kDetMaxPerSupercell
+    ERR_SORT = 8u,        // internal: the neighbourhood re-sort found inconsistent counts
 };
 
 // Deterministic current accumulation.  Every FP64 contribution v is split
@@ -192,17 +193,36 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 size_t rebin_scratch_bytes(int64_t n, const Geom& g);
 hipError_t launch_sort(const Geom& g, int64_t n, const unsigned* keys, const Parts& src,
                        unsigned* perm, int* sc_off, void* scratch, unsigned* err, hipStream_t s);
+// Particle arrays that a re-sort moves into the new order: count arrays of
+// 4- or 8-byte elements, src in the current order, dst another buffer.
+struct MoveArrays {
+    const void* src[8];
+    void* dst[8];
+    int bytes[8];
+    int count = 0;
+};
+// The same order for a re-sort after a push (keys from that push, old_off the
+// supercell offsets of the current order), computed per supercell from its
+// 27 neighbours' particles when every particle's new supercell is one of the
+// 27 around its old one (periodic x, S^3 <= 64).  Synchronises the stream
+// once to read the number of particles that moved farther; *done is false
+// (nothing else written) when there are any, or the grid is not supported,
+// and launch_sort must be used instead.  With move (count > 0) the arrays are
+// also written in the new order (dst[i] = src[perm[i]]), staged per supercell
+// through LDS.
+hipError_t launch_sort_local(const Geom& g, int64_t n, const unsigned* keys, const int* old_off,
+                             unsigned* perm, int* sc_off, void* scratch, unsigned* err,
+                             const MoveArrays* move, hipStream_t s, bool* done);
 // dst[i] = src[perm[i]] for the six state arrays and the ids.
 hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, const Parts& dst,
                           hipStream_t s);
 hipError_t launch_permute_ids(int64_t n, const unsigned* perm, const int64_t* src, int64_t* dst,
                               hipStream_t s);
-// The same permutation for a re-sort whose old order had the supercell
-// offsets old_off (each supercell's particles, mostly in one old block, are
-// staged through LDS); new_off: the offsets of the new order.
+// dst[i] = src[perm[i]] for the arrays of mv, for a re-sort whose old order had
+// the supercell offsets old_off (each supercell's particles, mostly in one old
+// block, are staged through LDS); new_off: the offsets of the new order.
 hipError_t launch_staged_permute(const Geom& g, int64_t n, const unsigned* perm, const int* old_off,
-                                const int* new_off, const Parts& src, const Parts& dst,
-                                hipStream_t s);
+                                const int* new_off, const MoveArrays& mv, hipStream_t s);
 
 // Adjoint of one step (FP64).  launch_fdtd_adjoint: the transposed Yee update
 // in place on (lE, lB), writing lJ (the adjoint of the step's current).

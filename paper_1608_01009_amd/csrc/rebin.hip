@@ -15,7 +15,11 @@
 //      round r holds the r-th particle of every cell with more than r, cells
 //      in order, so that a wave working through a round touches 64 different
 //      cells.  The result is the permutation perm (new index -> old index).
-// The particle data are not moved here: the next push reads through perm.
+// The particle data are not moved by this global sort: the next push reads
+// through perm, or the staged permutation moves them.  After a push, when no
+// particle moved beyond the 27 supercells around its old one, the same order
+// is built per supercell instead (the neighbourhood re-sort below), which
+// with dense supercells also moves the data.
 #include "pic_internal.h"
 
 namespace pic {
@@ -374,40 +378,433 @@ __global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n,
 // from LDS or, for the particles that arrived from other supercells (and
 // the part of an old block beyond the LDS buffer), from global memory.
 constexpr int kStageBlock = 512;
-constexpr int kStage = 4096;   // 8-byte values per array held in LDS
+constexpr int kStage = 4096;   // 8-byte values per array held in LDS (or 8192 4-byte ones)
 
 __global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
     const unsigned* __restrict__ perm, const int* __restrict__ old_off,
-    const int* __restrict__ new_off, Parts src, Parts dst) {
+    const int* __restrict__ new_off, MoveArrays mv) {
     __shared__ unsigned long long stage[kStage];
     const int s = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
     const int n0 = new_off[s], n1 = new_off[s + 1];
     if (n0 >= n1) return;
     const int o0 = old_off[s];
-    const int o1 = old_off[s + 1];
-    const unsigned cap = (unsigned)min(o1 - o0, kStage);
-    const unsigned long long* sa[7] = {
-        (const unsigned long long*)src.x,  (const unsigned long long*)src.y,
-        (const unsigned long long*)src.z,  (const unsigned long long*)src.ux,
-        (const unsigned long long*)src.uy, (const unsigned long long*)src.uz,
-        (const unsigned long long*)src.id};
-    unsigned long long* da[7] = {
-        (unsigned long long*)dst.x,  (unsigned long long*)dst.y,  (unsigned long long*)dst.z,
-        (unsigned long long*)dst.ux, (unsigned long long*)dst.uy, (unsigned long long*)dst.uz,
-        (unsigned long long*)dst.id};
+    const int ob = old_off[s + 1] - o0;
 #pragma unroll 1
-    for (int a = 0; a < 7; ++a) {
-        const unsigned long long* __restrict__ sp = sa[a];
-        unsigned long long* __restrict__ dp = da[a];
-        for (unsigned t = threadIdx.x; t < cap; t += kStageBlock) stage[t] = sp[o0 + (int)t];
-        __syncthreads();
+    for (int a = 0; a < mv.count; ++a) {
+        if (mv.bytes[a] == 8) {
+            const unsigned long long* __restrict__ sp = (const unsigned long long*)mv.src[a];
+            unsigned long long* __restrict__ dp = (unsigned long long*)mv.dst[a];
+            const unsigned cap = (unsigned)min(ob, kStage);
+            for (unsigned t = threadIdx.x; t < cap; t += kStageBlock) stage[t] = sp[o0 + (int)t];
+            __syncthreads();
 #pragma unroll 4
-        for (int i = n0 + (int)threadIdx.x; i < n1; i += kStageBlock) {
-            const unsigned j = perm[i];
-            const unsigned u = j - (unsigned)o0;
-            dp[i] = u < cap ? stage[u] : sp[j];
+            for (int i = n0 + (int)threadIdx.x; i < n1; i += kStageBlock) {
+                const unsigned j = perm[i];
+                const unsigned u = j - (unsigned)o0;
+                dp[i] = u < cap ? stage[u] : sp[j];
+            }
+        } else {
+            const unsigned* __restrict__ sp = (const unsigned*)mv.src[a];
+            unsigned* __restrict__ dp = (unsigned*)mv.dst[a];
+            unsigned* st = (unsigned*)stage;
+            const unsigned cap = (unsigned)min(ob, 2 * kStage);
+            for (unsigned t = threadIdx.x; t < cap; t += kStageBlock) st[t] = sp[o0 + (int)t];
+            __syncthreads();
+#pragma unroll 4
+            for (int i = n0 + (int)threadIdx.x; i < n1; i += kStageBlock) {
+                const unsigned j = perm[i];
+                const unsigned u = j - (unsigned)o0;
+                dp[i] = u < cap ? st[u] : sp[j];
+            }
         }
         __syncthreads();
+    }
+}
+
+// ---- neighbourhood re-sort ------------------------------------------------
+// Between re-sorts a particle drifts at most a few cells, so after a push its
+// new supercell is almost always one of the 27 around (periodically) the
+// supercell whose block of the current order holds it.  The order of the
+// stable sort by (supercell, cell) followed by the round interleave is then
+// built per supercell without a global sort:
+//   classify   per old supercell s': the direction (one of 27) of every
+//              particle's new supercell, counts per direction, and the
+//              block's slots partitioned by direction in slot order (stable);
+//              particles beyond the 27 are counted as distant;
+//   sizes      per new supercell: the sum of the counts directed at it by
+//              its (up to 27 distinct) neighbours; exclusive scan -> offsets;
+//   interleave per new supercell s: its incoming slots are the segments
+//              directed at it, taken in increasing order of the source
+//              supercell (= increasing slot, since the current order is
+//              grouped by supercell), which is the stable order; each
+//              particle's rank among its cell's particles follows from a
+//              running per-cell count, and its place in the rounds from the
+//              per-round masks of cells with more than r particles.
+constexpr int kNbrDirs = 28;     // 27 directions + distant
+constexpr int kNbrStride = 32;   // ints per supercell in the count table
+constexpr int kNbrDistant = 27;
+constexpr int kNbrMaxRounds = 512;
+
+struct NbrGeom {
+    int ns[3];
+    int nsc;
+    int s3shift;   // log2(S^3)
+    int sh0, sh1;  // log2 ns[0], log2 ns[1] when both are powers of two, else -1
+    float rns0, rns1;
+};
+
+// floor(a / m) for 0 <= a < 2^24, m >= 1: the float quotient is within one
+// of the exact one and is corrected by the remainder.
+__device__ __forceinline__ int div_small(int a, int m, float rm) {
+    int q = (int)((float)a * rm);
+    const int r = a - q * m;
+    q += (r >= m) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+}
+
+struct I3 {
+    int x, y, z;
+};
+
+__device__ __forceinline__ I3 sc_coords(int s, const NbrGeom& q) {
+    I3 c;
+    if (q.sh0 >= 0) {
+        c.x = s & (q.ns[0] - 1);
+        const int t = s >> q.sh0;
+        c.y = t & (q.ns[1] - 1);
+        c.z = t >> q.sh1;
+    } else {
+        const int t = div_small(s, q.ns[0], q.rns0);
+        c.x = s - t * q.ns[0];
+        c.z = div_small(t, q.ns[1], q.rns1);
+        c.y = t - c.z * q.ns[1];
+    }
+    return c;
+}
+
+// Direction code of the periodic offset dest - src along an axis of m
+// supercells (both in [0, m)): 0 (-1), 1 (0), 2 (+1), or 3 (farther).  With
+// m = 2 both neighbours are the same supercell and take code 2.
+__device__ __forceinline__ int axis_code(int dest, int src, int m) {
+    int v = dest - src;
+    v += v < 0 ? m : 0;
+    return v == 0 ? 1 : (v == 1 ? 2 : (v == m - 1 ? 0 : 3));
+}
+
+__device__ __forceinline__ int wrap_axis(int v, int m) {
+    v += v < 0 ? m : 0;
+    return v >= m ? v - m : v;
+}
+
+// Lanes whose value v (bits below nbits) equals this lane's, among the valid.
+__device__ __forceinline__ unsigned long long match_lanes(bool valid, unsigned v, int nbits) {
+    unsigned long long peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const unsigned long long bb = __ballot(valid && ((v >> b) & 1u));
+        peers &= ((v >> b) & 1u) ? bb : ~bb;
+    }
+    return peers;
+}
+
+constexpr int kNbrBlock = 512;
+constexpr int kNbrWaves = kNbrBlock / 64;
+constexpr int kNbrKeepDirs = 16384;   // directions of an old block kept in LDS
+constexpr int kNbrKeep = 4096;        // incoming particles of a new supercell kept in LDS
+
+// Each wave takes a contiguous chunk of [0, n) (whole rounds of 64, waves in
+// order), so that per-wave counts and their exclusive prefix over the waves
+// give stable positions without a workgroup barrier per round.
+template <int WAVES>
+__device__ __forceinline__ void wave_chunk(int n, int w, int* c0, int* c1) {
+    const int per = ((n + WAVES * 64 - 1) / (WAVES * 64)) * 64;
+    *c0 = min(n, w * per);
+    *c1 = min(n, *c0 + per);
+}
+
+// The supercell that direction dir of supercell sc points to.
+__device__ __forceinline__ int nbr_dest(const NbrGeom& q, I3 sc, int dir) {
+    const int x = wrap_axis(sc.x + dir % 3 - 1, q.ns[0]);
+    const int y = wrap_axis(sc.y + (dir / 3) % 3 - 1, q.ns[1]);
+    const int z = wrap_axis(sc.z + dir / 9 - 1, q.ns[2]);
+    return x + q.ns[0] * (y + q.ns[1] * z);
+}
+
+__global__ void __launch_bounds__(kNbrBlock) nbr_classify_kernel(
+    NbrGeom q, const unsigned* __restrict__ key, const int* __restrict__ old_off,
+    int* __restrict__ cnt_out, unsigned* __restrict__ list, unsigned* __restrict__ size,
+    unsigned* __restrict__ distant) {
+    __shared__ unsigned char dirs[kNbrKeepDirs];
+    __shared__ unsigned wcnt[kNbrWaves][kNbrStride];
+    __shared__ unsigned tot[kNbrStride];
+    __shared__ unsigned seg[kNbrStride];
+    const int s = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
+    const int o0 = old_off[s];
+    const int nb = old_off[s + 1] - o0;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const bool keep = nb <= kNbrKeepDirs;
+    const I3 sc = sc_coords(s, q);
+    for (int t = threadIdx.x; t < kNbrWaves * kNbrStride; t += kNbrBlock) (&wcnt[0][0])[t] = 0u;
+    __syncthreads();
+    auto dir_of = [&](int i) -> unsigned {
+        const I3 d = sc_coords((int)(key[i] >> q.s3shift), q);
+        const int cx = axis_code(d.x, sc.x, q.ns[0]);
+        const int cy = axis_code(d.y, sc.y, q.ns[1]);
+        const int cz = axis_code(d.z, sc.z, q.ns[2]);
+        const bool far = (cx == 3) | (cy == 3) | (cz == 3);
+        return far ? (unsigned)kNbrDistant : (unsigned)(cx + 3 * cy + 9 * cz);
+    };
+    int c0, c1;
+    wave_chunk<kNbrWaves>(nb, w, &c0, &c1);
+    // directions first (independent loads, several in flight), then the
+    // per-wave counts per direction (the leader of each direction's lanes
+    // adds; one wave writes its own row in program order)
+    if (keep) {
+#pragma unroll 4
+        for (int t = c0 + lane; t < c1; t += 64) dirs[t] = (unsigned char)dir_of(o0 + t);
+    }
+    for (int t0 = c0; t0 < c1; t0 += 64) {
+        const int t = t0 + lane;
+        const bool valid = t < c1;
+        const unsigned dir = valid ? (keep ? (unsigned)dirs[t] : dir_of(o0 + t)) : 0u;
+        const unsigned long long peers = match_lanes(valid, dir, 5);
+        if (valid && __popcll(peers & lt) == 0) wcnt[w][dir] += (unsigned)__popcll(peers);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNbrDirs) {
+        unsigned a = 0;
+        for (int ww = 0; ww < kNbrWaves; ++ww) a += wcnt[ww][threadIdx.x];
+        tot[threadIdx.x] = a;
+        // the new supercells' sizes, summed over their sources
+        if (threadIdx.x < kNbrDistant && a > 0) atomicAdd(&size[nbr_dest(q, sc, threadIdx.x)], a);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned r = 0;
+        for (int d = 0; d < kNbrDirs; ++d) {
+            seg[d] = r;
+            r += tot[d];
+        }
+        seg[kNbrDirs] = r;
+        if (tot[kNbrDistant] > 0) atomicAdd(distant, tot[kNbrDistant]);
+    }
+    __syncthreads();
+    // segment starts in the block per direction (and the block size last)
+    if (threadIdx.x <= kNbrDirs) cnt_out[(size_t)s * kNbrStride + threadIdx.x] = (int)seg[threadIdx.x];
+    if (threadIdx.x < kNbrDirs) {
+        unsigned b = seg[threadIdx.x];
+        for (int ww = 0; ww < kNbrWaves; ++ww) {
+            const unsigned c = wcnt[ww][threadIdx.x];
+            wcnt[ww][threadIdx.x] = b;
+            b += c;
+        }
+    }
+    __syncthreads();
+    // the block's slots partitioned by direction, in slot order
+    for (int t0 = c0; t0 < c1; t0 += 64) {
+        const int t = t0 + lane;
+        const bool valid = t < c1;
+        const unsigned dir = valid ? (keep ? (unsigned)dirs[t] : dir_of(o0 + t)) : 0u;
+        const unsigned long long peers = match_lanes(valid, dir, 5);
+        const unsigned rank = valid ? (unsigned)__popcll(peers & lt) : 0u;
+        const unsigned base = valid ? wcnt[w][dir] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) wcnt[w][dir] = base + (unsigned)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        if (valid) list[o0 + (int)(base + rank)] = (unsigned)(o0 + t);
+    }
+}
+
+// The distinct neighbours that can send particles to supercell s: along an
+// axis of m supercells the offsets -1, 0, +1 (m >= 3), 0, +1 (m = 2) or 0
+// (m = 1).  For neighbour k (0..26 in x-fastest order of the offsets) it
+// returns false if the offset is not used, else the source supercell and the
+// direction code under which that source classified particles bound for s.
+__device__ __forceinline__ bool nbr_source(const NbrGeom& q, I3 sc, int k, int* src, int* dir) {
+    const int cx = k % 3 - 1, cy = (k / 3) % 3 - 1, cz = k / 9 - 1;
+    auto used = [](int c, int m) { return c >= (m >= 3 ? -1 : 0) && c <= (m >= 2 ? 1 : 0); };
+    if (!used(cx, q.ns[0]) || !used(cy, q.ns[1]) || !used(cz, q.ns[2])) return false;
+    const int x = wrap_axis(sc.x - cx, q.ns[0]);
+    const int y = wrap_axis(sc.y - cy, q.ns[1]);
+    const int z = wrap_axis(sc.z - cz, q.ns[2]);
+    *src = x + q.ns[0] * (y + q.ns[1] * z);
+    *dir = axis_code(sc.x, x, q.ns[0]) + 3 * axis_code(sc.y, y, q.ns[1]) +
+           9 * axis_code(sc.z, z, q.ns[2]);
+    return true;
+}
+
+// Per new supercell: its incoming slots (the segments directed at it, in
+// increasing order of the source supercell), their ranks in their cells and
+// places in the rounds -> perm.
+constexpr int kNbrMoveBlock = 512;
+constexpr int kNbrMoveWaves = kNbrMoveBlock / 64;
+
+__global__ void __launch_bounds__(kNbrMoveBlock) nbr_interleave_kernel(
+    NbrGeom q, const unsigned* __restrict__ key, const int* __restrict__ old_off,
+    const int* __restrict__ seg, const unsigned* __restrict__ list,
+    const int* __restrict__ new_off, unsigned* __restrict__ tmp_j, unsigned* __restrict__ tmp_c,
+    unsigned* __restrict__ perm, unsigned* __restrict__ err) {
+    __shared__ unsigned lj[kNbrKeep];
+    __shared__ unsigned char lc[kNbrKeep];
+    __shared__ int k_src[27], k_start[27], k_cnt[27];
+    __shared__ int o_start[27], o_pre[28];
+    __shared__ int nsrc_s;
+    __shared__ unsigned wcnt[kNbrMoveWaves][64];
+    __shared__ unsigned ccount[64];
+    __shared__ int rstart[kNbrMaxRounds + 1];
+    __shared__ unsigned long long rmask[kNbrMaxRounds];
+    __shared__ int maxc_s;
+    const int s = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
+    const int n0 = new_off[s], n1 = new_off[s + 1];
+    if (n0 >= n1) return;
+    const int S3 = 1 << q.s3shift;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const I3 sc = sc_coords(s, q);
+    if (threadIdx.x < 27) {
+        const int k = threadIdx.x;
+        int src = -1, dir = 0;
+        if (nbr_source(q, sc, k, &src, &dir)) {
+            const int* c = seg + (size_t)src * kNbrStride;
+            const int a = c[dir], b = c[dir + 1];
+            k_start[k] = old_off[src] + a;
+            k_cnt[k] = b - a;
+        } else {
+            src = -1;
+            k_start[k] = 0;
+            k_cnt[k] = 0;
+        }
+        k_src[k] = src;
+    }
+    for (int t = threadIdx.x; t < kNbrMoveWaves * 64; t += kNbrMoveBlock) (&wcnt[0][0])[t] = 0u;
+    __syncthreads();
+    if (threadIdx.x < 27 && k_src[threadIdx.x] >= 0) {
+        // place of this source in increasing source order (sources distinct)
+        const int me = k_src[threadIdx.x];
+        int r = 0;
+        for (int k = 0; k < 27; ++k) r += (k_src[k] >= 0 && k_src[k] < me) ? 1 : 0;
+        o_start[r] = k_start[threadIdx.x];
+        o_pre[r + 1] = k_cnt[threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nsrc = 0;
+        for (int k = 0; k < 27; ++k) nsrc += k_src[k] >= 0 ? 1 : 0;
+        o_pre[0] = 0;
+        for (int r = 0; r < nsrc; ++r) o_pre[r + 1] += o_pre[r];
+        nsrc_s = nsrc;
+        if (o_pre[nsrc] != n1 - n0) atomicOr(err, ERR_SORT);
+    }
+    __syncthreads();
+    const int nsrc = nsrc_s;
+    const int N = min(n1 - n0, o_pre[nsrc]);
+    const unsigned kb = (unsigned)s << q.s3shift;
+    // incoming slots and their cells, in LDS when they fit
+    const bool keep = N <= kNbrKeep;
+    unsigned* jb = keep ? lj : tmp_j + n0;
+    unsigned char* cb = keep ? lc : (unsigned char*)(tmp_c + n0);
+    int c0, c1;
+    wave_chunk<kNbrMoveWaves>(N, w, &c0, &c1);
+    {
+        // the source segment holding t is the last r < nsrc with o_pre[r] <= t;
+        // a lane's t grows by 64 per round, so after one binary search its
+        // segment only moves forward
+        int lo = 0;
+        {
+            const int t = c0 + lane;
+            int hi = nsrc;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (o_pre[mid] <= t)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+        }
+#pragma unroll 4
+        for (int t = c0 + lane; t < c1; t += 64) {
+            while (lo + 1 < nsrc && o_pre[lo + 1] <= t) ++lo;
+            jb[t] = list[o_start[lo] + (t - o_pre[lo])];
+        }
+        // their cells (independent loads)
+#pragma unroll 4
+        for (int t = c0 + lane; t < c1; t += 64) {
+            unsigned cell = key[jb[t]] - kb;
+            if (cell >= (unsigned)S3) {
+                atomicOr(err, ERR_SORT);
+                cell = 0u;
+            }
+            cb[t] = (unsigned char)cell;
+        }
+    }
+    for (int t0 = c0; t0 < c1; t0 += 64) {
+        const int t = t0 + lane;
+        const bool valid = t < c1;
+        const unsigned cell = valid ? (unsigned)cb[t] : 0u;
+        const unsigned long long peers = match_lanes(valid, cell, q.s3shift);
+        if (valid && __popcll(peers & lt) == 0) wcnt[w][cell] += (unsigned)__popcll(peers);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // per cell: the exclusive prefix over the waves, and the total
+        unsigned b = 0;
+        for (int ww = 0; ww < kNbrMoveWaves; ++ww) {
+            const unsigned c = wcnt[ww][threadIdx.x];
+            wcnt[ww][threadIdx.x] = b;
+            b += c;
+        }
+        ccount[threadIdx.x] = b;
+        const int c = (int)threadIdx.x < S3 ? (int)b : 0;
+        int mx = c;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int t = __shfl_xor(mx, o, 64);
+            mx = t > mx ? t : mx;
+        }
+        if (threadIdx.x == 0) maxc_s = mx;
+        if (mx <= kNbrMaxRounds) {
+            int acc = 0;
+            for (int r = 0; r < mx; ++r) {
+                const unsigned long long m = __ballot(c > r);
+                if (threadIdx.x == 0) {
+                    rmask[r] = m;
+                    rstart[r] = acc;
+                }
+                acc += __popcll(m);
+            }
+        }
+    }
+    __syncthreads();
+    const int maxc = maxc_s;
+    for (int t0 = c0; t0 < c1; t0 += 64) {
+        const int t = t0 + lane;
+        const bool valid = t < c1;
+        const unsigned cell = valid ? (unsigned)cb[t] : 0u;
+        const unsigned j = valid ? jb[t] : 0u;
+        const unsigned long long peers = match_lanes(valid, cell, q.s3shift);
+        const unsigned rw = valid ? (unsigned)__popcll(peers & lt) : 0u;
+        const unsigned base = valid ? wcnt[w][cell] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rw == 0) wcnt[w][cell] = base + (unsigned)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        if (!valid) continue;
+        const int rank = (int)(base + rw);
+        int pos = 0;
+        if (maxc <= kNbrMaxRounds) {
+            pos = rstart[rank] + __popcll(rmask[rank] & ((1ull << cell) - 1ull));
+        } else {
+            for (int l = 0; l < S3; ++l) {
+                const int cl = (int)ccount[l];
+                pos += (cl < rank ? cl : rank) + ((l < (int)cell && cl > rank) ? 1 : 0);
+            }
+        }
+        if (pos < N)
+            perm[n0 + pos] = j;
+        else
+            atomicOr(err, ERR_SORT);
     }
 }
 
@@ -440,9 +837,13 @@ struct Scratch {
     unsigned* hist;
     unsigned* offs;
     unsigned* sums;
+    int* nbr_cnt;        // nsc x kNbrStride segment starts per direction
+    unsigned* nbr_size;  // nsc + 1 sizes
+    unsigned* nbr_sums;  // block sums of their scan
+    unsigned* nbr_far;   // particles beyond the 27 neighbours
 };
 
-Scratch carve(void* base, int64_t n) {
+Scratch carve(void* base, int64_t n, int nsc) {
     const int nb = nblk(n, kTile);
     const int64_t hn = (int64_t)(1 << kMaxBits) * nb;
     char* p = (char*)base;
@@ -454,7 +855,11 @@ Scratch carve(void* base, int64_t n) {
     s.v1 = (unsigned*)p; p += kb;
     s.hist = (unsigned*)p; p += align_up((size_t)hn * 4);
     s.offs = (unsigned*)p; p += align_up((size_t)hn * 4);
-    s.sums = (unsigned*)p;
+    s.sums = (unsigned*)p; p += align_up((size_t)nblk(hn, kTile) * 4);
+    s.nbr_cnt = (int*)p; p += align_up((size_t)nsc * kNbrStride * 4);
+    s.nbr_size = (unsigned*)p; p += (size_t)(nsc + 1) * 4;
+    s.nbr_far = (unsigned*)p; p = (char*)s.nbr_size + align_up((size_t)(nsc + 2) * 4);
+    s.nbr_sums = (unsigned*)p;
     return s;
 }
 
@@ -494,11 +899,12 @@ void radix_pass_bits(int bits, const unsigned* kin, const unsigned* vin, unsigne
 }  // namespace
 
 size_t rebin_scratch_bytes(int64_t n, const Geom& g) {
-    (void)g;
     const int nb = nblk(n, kTile);
     const int64_t hn = (int64_t)(1 << kMaxBits) * nb;
     const size_t kb = align_up((size_t)(n > 0 ? n : 1) * 4);
-    return 4 * kb + 2 * align_up((size_t)hn * 4) + align_up((size_t)nblk(hn, kTile) * 4) + 256;
+    return 4 * kb + 2 * align_up((size_t)hn * 4) + align_up((size_t)nblk(hn, kTile) * 4) +
+           align_up((size_t)g.nsc * kNbrStride * 4) + align_up((size_t)(g.nsc + 2) * 4) +
+           align_up((size_t)nblk((int64_t)g.nsc + 1, kTile) * 4) + 256;
 }
 
 hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const Parts& src,
@@ -511,7 +917,7 @@ hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const P
                            0, S3, g.nsc, sc_off);
         return hipGetLastError();
     }
-    Scratch sc = carve(scratch, n);
+    Scratch sc = carve(scratch, n, g.nsc);
     if (!keys) {
         hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, g, n, src.x, src.y,
                            src.z, src.ux, src.uy, src.uz, sc.k0, err);
@@ -551,6 +957,55 @@ hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const P
     return hipGetLastError();
 }
 
+hipError_t launch_sort_local(const Geom& g, int64_t n64, const unsigned* keys, const int* old_off,
+                             unsigned* perm, int* sc_off, void* scratch, unsigned* err,
+                             const MoveArrays* move, hipStream_t s, bool* done) {
+    *done = false;
+    const int n = (int)n64;
+    const int S3 = g.S * g.S * g.S;
+    if (n <= 0 || keys == nullptr || g.absorb_x || S3 > 64 || (S3 & (S3 - 1)) != 0 ||
+        g.nsc >= (1 << 24))
+        return hipSuccess;
+    Scratch sc = carve(scratch, n, g.nsc);
+    NbrGeom q;
+    for (int a = 0; a < 3; ++a) q.ns[a] = g.ns[a];
+    q.nsc = g.nsc;
+    q.s3shift = __builtin_ctz((unsigned)S3);
+    const bool pow2 = (g.ns[0] & (g.ns[0] - 1)) == 0 && (g.ns[1] & (g.ns[1] - 1)) == 0;
+    q.sh0 = pow2 ? __builtin_ctz((unsigned)g.ns[0]) : -1;
+    q.sh1 = pow2 ? __builtin_ctz((unsigned)g.ns[1]) : -1;
+    q.rns0 = 1.0f / (float)g.ns[0];
+    q.rns1 = 1.0f / (float)g.ns[1];
+    // the sizes (summed by the classification) and the distant count
+    hipError_t e = hipMemsetAsync(sc.nbr_size, 0, (size_t)(g.nsc + 2) * sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nbr_classify_kernel, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys, old_off,
+                       sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    unsigned far = 0;
+    if ((e = hipMemcpyAsync(&far, sc.nbr_far, sizeof(unsigned), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return e;
+    if (far != 0) return hipSuccess;   // the global sort takes over
+    const int m = g.nsc + 1;
+    const int nsum = nblk(m, kTile);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.nbr_size, m,
+                       sc.nbr_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.nbr_sums, nsum);
+    hipLaunchKernelGGL(scan_down_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.nbr_size, m,
+                       sc.nbr_sums, (unsigned*)sc_off);
+    hipLaunchKernelGGL(nbr_interleave_kernel, dim3(g.nsc), dim3(kNbrMoveBlock), 0, s, q, keys,
+                       old_off, (const int*)sc.nbr_cnt, (const unsigned*)sc.k1, (const int*)sc_off,
+                       sc.k0, sc.v0, perm, err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (move && move->count > 0 &&
+        (e = launch_staged_permute(g, n, perm, old_off, sc_off, *move, s)) != hipSuccess)
+        return e;
+    *done = true;
+    return hipSuccess;
+}
+
 hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, const Parts& dst,
                           hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -560,11 +1015,11 @@ hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, con
 }
 
 hipError_t launch_staged_permute(const Geom& g, int64_t n, const unsigned* perm, const int* old_off,
-                                const int* new_off, const Parts& src, const Parts& dst,
-                                hipStream_t s) {
-    if (n <= 0 || g.nsc <= 0) return hipSuccess;
+                                const int* new_off, const MoveArrays& mv, hipStream_t s) {
+    if (n <= 0 || g.nsc <= 0 || mv.count == 0) return hipSuccess;
+    if (mv.count > 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(staged_permute_kernel, dim3(g.nsc), dim3(kStageBlock), 0, s, perm, old_off,
-                       new_off, src, dst);
+                       new_off, mv);
     return hipGetLastError();
 }
 

@@ -116,11 +116,41 @@ def test_fields_only_vacuum_step():
     one_step_parity(wl, [0, 1, 3])[1].close()
 
 
-@pytest.mark.parametrize("n,ppc", [((16, 16, 16), 64), ((8, 8, 8), 200)])
+@pytest.mark.parametrize("n,ppc", [((16, 16, 16), 64), ((8, 8, 8), 200), ((8, 8, 8), 300)])
 def test_dense_supercells_staged_resort(n, ppc):
-    # 4,096 and 12,800 particles per 4^3 supercell: the re-sort order is
-    # applied by the LDS-staged permutation (the second case also overflows
-    # its 4,096-value buffer); steps 19 (ends with the re-sort), 20 (the push
-    # after it, in stored order) and 21
+    # 4,096, 12,800 and 19,200 particles per 4^3 supercell: the re-sort order
+    # is applied by the LDS-staged permutation (the larger cases overflow its
+    # 4,096-value buffer, and the buffers of the neighbourhood re-sort for
+    # 4,096 incoming particles and 16,384 classified ones); steps 19 (ends
+    # with the re-sort), 20 (the push after it, in stored order) and 21
     wl = W.scaled(2, n, ppc, seed=70 + ppc)
     one_step_parity(wl, [19, 20, 21])[1].close()
+
+
+def test_resort_with_particles_beyond_the_neighbouring_supercells():
+    # every 16th particle (all in odd x cells: the recipe places 2 per cell in
+    # x-fastest order) starts at about 0.99 c along x and moves about 2.9
+    # cells before the first re-sort, most crossing more than one 2-cell
+    # supercell:
+    # such a re-sort cannot take the per-supercell (neighbourhood) path and
+    # falls back to the global radix sort; the order after it (step 10) and
+    # after the next one (step 20) is checked against the oracle
+    wl = W.plasma("beam-resort", (32, 16, 16), 2, 0.02, seed=52, noise=1e-2, S=2, R=10)
+    sp = wl.species[0]
+    rng = np.random.default_rng(53)
+    sp.ux[3::16] = 6.0 + rng.random(len(sp.ux[3::16]))
+    # the case is what it claims: some particle's supercell moves by more
+    # than one between the load and the first re-sort
+    sim = pic.Simulation.from_workload(wl)
+    a = sim.particles(0)
+    sim.step(10)
+    b = sim.particles(0)
+    sim.close()
+    ia, ib = np.argsort(a["id"][:a["n"]]), np.argsort(b["id"][:b["n"]])
+    moved = 0
+    for key, ns in (("x", 16), ("y", 8), ("z", 8)):
+        d = (np.floor(b[key][ib] / 2.0) - np.floor(a[key][ia] / 2.0)) % ns
+        moved += int(np.sum((d > 1) & (d < ns - 1)))
+    log(f"  particles beyond the neighbouring supercells at the first re-sort: {moved}")
+    assert moved > 0
+    one_step_parity(wl, [9, 10, 19, 20])[1].close()
