@@ -380,6 +380,57 @@ __global__ void __launch_bounds__(kBlock) permute_ids_kernel(int n,
 constexpr int kStageBlock = 512;
 constexpr int kStage = 4096;   // 8-byte values per array held in LDS (or 8192 4-byte ones)
 
+// One array of the staged permutation: the old block staged in LDS (up to
+// CAP elements), then dst[i] = src[perm[i]] for the new block, from LDS when
+// the source is in the staged part.  The loads of a thread's elements are
+// issued together (KB per round) before their values are used, so that their
+// latencies overlap.
+template <class T, int CAP>
+__device__ __forceinline__ void staged_move(const T* __restrict__ sp, T* __restrict__ dp,
+                                            T* stage, const unsigned* __restrict__ perm, int o0,
+                                            int ob, int n0, int n1) {
+    constexpr int KB = 8;
+    const unsigned cap = (unsigned)min(ob, CAP);
+    for (int b = 0; b < (int)cap; b += KB * kStageBlock) {
+        T v[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const unsigned t = (unsigned)(b + k * kStageBlock) + threadIdx.x;
+            if (t < cap) v[k] = sp[o0 + (int)t];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const unsigned t = (unsigned)(b + k * kStageBlock) + threadIdx.x;
+            if (t < cap) stage[t] = v[k];
+        }
+    }
+    __syncthreads();
+    for (int b = n0; b < n1; b += KB * kStageBlock) {
+        unsigned jj[KB];
+        T v[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int i = b + k * kStageBlock + (int)threadIdx.x;
+            jj[k] = i < n1 ? perm[i] : (unsigned)o0;
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const unsigned u = jj[k] - (unsigned)o0;
+            if (u >= cap) v[k] = sp[jj[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const unsigned u = jj[k] - (unsigned)o0;
+            if (u < cap) v[k] = stage[u];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int i = b + k * kStageBlock + (int)threadIdx.x;
+            if (i < n1) dp[i] = v[k];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
     const unsigned* __restrict__ perm, const int* __restrict__ old_off,
     const int* __restrict__ new_off, MoveArrays mv) {
@@ -391,32 +442,13 @@ __global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
     const int ob = old_off[s + 1] - o0;
 #pragma unroll 1
     for (int a = 0; a < mv.count; ++a) {
-        if (mv.bytes[a] == 8) {
-            const unsigned long long* __restrict__ sp = (const unsigned long long*)mv.src[a];
-            unsigned long long* __restrict__ dp = (unsigned long long*)mv.dst[a];
-            const unsigned cap = (unsigned)min(ob, kStage);
-            for (unsigned t = threadIdx.x; t < cap; t += kStageBlock) stage[t] = sp[o0 + (int)t];
-            __syncthreads();
-#pragma unroll 4
-            for (int i = n0 + (int)threadIdx.x; i < n1; i += kStageBlock) {
-                const unsigned j = perm[i];
-                const unsigned u = j - (unsigned)o0;
-                dp[i] = u < cap ? stage[u] : sp[j];
-            }
-        } else {
-            const unsigned* __restrict__ sp = (const unsigned*)mv.src[a];
-            unsigned* __restrict__ dp = (unsigned*)mv.dst[a];
-            unsigned* st = (unsigned*)stage;
-            const unsigned cap = (unsigned)min(ob, 2 * kStage);
-            for (unsigned t = threadIdx.x; t < cap; t += kStageBlock) st[t] = sp[o0 + (int)t];
-            __syncthreads();
-#pragma unroll 4
-            for (int i = n0 + (int)threadIdx.x; i < n1; i += kStageBlock) {
-                const unsigned j = perm[i];
-                const unsigned u = j - (unsigned)o0;
-                dp[i] = u < cap ? st[u] : sp[j];
-            }
-        }
+        if (mv.bytes[a] == 8)
+            staged_move<unsigned long long, kStage>((const unsigned long long*)mv.src[a],
+                                                    (unsigned long long*)mv.dst[a], stage, perm,
+                                                    o0, ob, n0, n1);
+        else
+            staged_move<unsigned, 2 * kStage>((const unsigned*)mv.src[a], (unsigned*)mv.dst[a],
+                                              (unsigned*)stage, perm, o0, ob, n0, n1);
         __syncthreads();
     }
 }
@@ -467,9 +499,10 @@ struct I3 {
     int x, y, z;
 };
 
+template <bool POW2>
 __device__ __forceinline__ I3 sc_coords(int s, const NbrGeom& q) {
     I3 c;
-    if (q.sh0 >= 0) {
+    if (POW2) {
         c.x = s & (q.ns[0] - 1);
         const int t = s >> q.sh0;
         c.y = t & (q.ns[1] - 1);
@@ -530,6 +563,7 @@ __device__ __forceinline__ int nbr_dest(const NbrGeom& q, I3 sc, int dir) {
     return x + q.ns[0] * (y + q.ns[1] * z);
 }
 
+template <bool POW2>
 __global__ void __launch_bounds__(kNbrBlock) nbr_classify_kernel(
     NbrGeom q, const unsigned* __restrict__ key, const int* __restrict__ old_off,
     int* __restrict__ cnt_out, unsigned* __restrict__ list, unsigned* __restrict__ size,
@@ -545,25 +579,38 @@ __global__ void __launch_bounds__(kNbrBlock) nbr_classify_kernel(
     const int w = threadIdx.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const bool keep = nb <= kNbrKeepDirs;
-    const I3 sc = sc_coords(s, q);
+    const I3 sc = sc_coords<POW2>(s, q);
     for (int t = threadIdx.x; t < kNbrWaves * kNbrStride; t += kNbrBlock) (&wcnt[0][0])[t] = 0u;
     __syncthreads();
-    auto dir_of = [&](int i) -> unsigned {
-        const I3 d = sc_coords((int)(key[i] >> q.s3shift), q);
+    auto dir_of_key = [&](unsigned k) -> unsigned {
+        const I3 d = sc_coords<POW2>((int)(k >> q.s3shift), q);
         const int cx = axis_code(d.x, sc.x, q.ns[0]);
         const int cy = axis_code(d.y, sc.y, q.ns[1]);
         const int cz = axis_code(d.z, sc.z, q.ns[2]);
         const bool far = (cx == 3) | (cy == 3) | (cz == 3);
         return far ? (unsigned)kNbrDistant : (unsigned)(cx + 3 * cy + 9 * cz);
     };
+    auto dir_of = [&](int i) -> unsigned { return dir_of_key(key[i]); };
     int c0, c1;
     wave_chunk<kNbrWaves>(nb, w, &c0, &c1);
     // directions first (independent loads, several in flight), then the
     // per-wave counts per direction (the leader of each direction's lanes
     // adds; one wave writes its own row in program order)
     if (keep) {
-#pragma unroll 4
-        for (int t = c0 + lane; t < c1; t += 64) dirs[t] = (unsigned char)dir_of(o0 + t);
+        constexpr int KB = 8;
+        for (int b = c0 + lane; b < c1; b += 64 * KB) {
+            unsigned kv[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int t = b + 64 * k;
+                if (t < c1) kv[k] = key[o0 + t];
+            }
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int t = b + 64 * k;
+                if (t < c1) dirs[t] = (unsigned char)dir_of_key(kv[k]);
+            }
+        }
     }
     for (int t0 = c0; t0 < c1; t0 += 64) {
         const int t = t0 + lane;
@@ -663,7 +710,7 @@ __global__ void __launch_bounds__(kNbrMoveBlock) nbr_interleave_kernel(
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const I3 sc = sc_coords(s, q);
+    const I3 sc = q.sh0 >= 0 ? sc_coords<true>(s, q) : sc_coords<false>(s, q);
     if (threadIdx.x < 27) {
         const int k = threadIdx.x;
         int src = -1, dir = 0;
@@ -724,21 +771,37 @@ __global__ void __launch_bounds__(kNbrMoveBlock) nbr_interleave_kernel(
                     hi = mid;
             }
         }
-#pragma unroll 4
-        for (int t = c0 + lane; t < c1; t += 64) {
-            while (lo + 1 < nsrc && o_pre[lo + 1] <= t) ++lo;
-            jb[t] = list[o_start[lo] + (t - o_pre[lo])];
-        }
-        // their cells (independent loads)
-#pragma unroll 4
-        for (int t = c0 + lane; t < c1; t += 64) {
-            unsigned cell = key[jb[t]] - kb;
-            if (cell >= (unsigned)S3) {
-                atomicOr(err, ERR_SORT);
-                cell = 0u;
+        constexpr int KB = 8;
+        bool bad = false;
+        for (int b = c0 + lane; b < c1; b += 64 * KB) {
+            int ix[KB];
+            unsigned jv[KB], kv[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int t = b + 64 * k;
+                while (lo + 1 < nsrc && o_pre[lo + 1] <= t) ++lo;
+                ix[k] = o_start[lo] + (t - o_pre[lo]);
             }
-            cb[t] = (unsigned char)cell;
+            // the slots, then their keys: each group of loads issued together
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                if (b + 64 * k < c1) jv[k] = list[ix[k]];
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                if (b + 64 * k < c1) kv[k] = key[jv[k]];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int t = b + 64 * k;
+                if (t < c1) {
+                    unsigned cell = kv[k] - kb;
+                    bad = bad || cell >= (unsigned)S3;
+                    cell = cell < (unsigned)S3 ? cell : 0u;
+                    jb[t] = jv[k];
+                    cb[t] = (unsigned char)cell;
+                }
+            }
         }
+        if (bad) atomicOr(err, ERR_SORT);
     }
     for (int t0 = c0; t0 < c1; t0 += 64) {
         const int t = t0 + lane;
@@ -979,8 +1042,12 @@ hipError_t launch_sort_local(const Geom& g, int64_t n64, const unsigned* keys, c
     // the sizes (summed by the classification) and the distant count
     hipError_t e = hipMemsetAsync(sc.nbr_size, 0, (size_t)(g.nsc + 2) * sizeof(unsigned), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nbr_classify_kernel, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys, old_off,
-                       sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
+    if (pow2)
+        hipLaunchKernelGGL(nbr_classify_kernel<true>, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys,
+                           old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
+    else
+        hipLaunchKernelGGL(nbr_classify_kernel<false>, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys,
+                           old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     unsigned far = 0;
     if ((e = hipMemcpyAsync(&far, sc.nbr_far, sizeof(unsigned), hipMemcpyDeviceToHost, s)) !=
