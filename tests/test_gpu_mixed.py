@@ -293,3 +293,23 @@ def test_precision_variant_full_size_128c_32ppc():
     assert rel["WE"] <= 1e-6 and rel["WB"] <= 1e-5, rel
     assert rel["K"] <= 1e-8, rel
     assert max(mom) <= 2e-7, mom
+
+
+@pytest.mark.parametrize("n,ppc", [((16, 16, 16), 64), ((8, 8, 8), 300)])
+def test_mixed_dense_supercells_resort(n, ppc):
+    # 4,096 and 19,200 particles per supercell: the neighbourhood re-sort
+    # moves the packed arrays with the LDS-staged permutation (the second
+    # case beyond its buffers); steps 19 (ends with the re-sort), 20, 21
+    wl = W.scaled(2, n, ppc, seed=170 + ppc)
+    _run(wl, [19, 20, 21], _against_mixed_oracle)
+
+
+def test_mixed_resort_with_particles_beyond_the_neighbouring_supercells():
+    # a beam of every sixteenth particle at about 0.99 c crosses two 2-cell
+    # supercells before the first re-sort: the global sort takes over (the
+    # FP64 case in test_gpu_parity checks that the crossing happens)
+    wl = W.plasma("beam-resort-mixed", (32, 16, 16), 2, 0.02, seed=52, noise=1e-2, S=2, R=10)
+    sp = wl.species[0]
+    rng = np.random.default_rng(53)
+    sp.ux[3::16] = 6.0 + rng.random(len(sp.ux[3::16]))
+    _run(wl, [9, 10, 19, 20], _against_mixed_oracle)

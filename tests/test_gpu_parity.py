@@ -154,3 +154,18 @@ def test_resort_with_particles_beyond_the_neighbouring_supercells():
     log(f"  particles beyond the neighbouring supercells at the first re-sort: {moved}")
     assert moved > 0
     one_step_parity(wl, [9, 10, 19, 20])[1].close()
+
+
+def test_two_dense_species_resort():
+    # electrons and ions, 6,400 of each per 4^3 supercell: both are moved by
+    # their re-sort (neighbourhood order, staged permutation) and the step
+    # after it pushes both species over one tile load per supercell
+    base = W.scaled(2, (8, 8, 8), 100, seed=80)
+    ions = W.scaled(2, (8, 8, 8), 100, seed=81)
+    sp_i = ions.species[0]
+    sp_i.charge, sp_i.mass = 1.0, 1836.0
+    sp_i.ux *= 0.02
+    sp_i.uy *= 0.02
+    sp_i.uz *= 0.02
+    base.species.append(sp_i)
+    one_step_parity(base, [19, 20, 21])[1].close()
