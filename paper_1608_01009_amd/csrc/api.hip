@@ -105,6 +105,8 @@ struct pic_ctx {
     int far_phase = 0;
     int pair_phase = 0;            // counters far_n[4..7] of the two-species launch
     unsigned* h_err = nullptr;
+    unsigned* h_far = nullptr;     // pinned: distant-particle count of the last re-sort
+    hipEvent_t ev_sort = nullptr;  // recorded after that count's copy
     double* rho = nullptr;
     double* tmp = nullptr;
     double* G0 = nullptr;
@@ -181,6 +183,10 @@ void release(pic_ctx* c) {
     c->allocs.clear();
     if (c->h_err) (void)hipHostFree(c->h_err);
     c->h_err = nullptr;
+    if (c->h_far) (void)hipHostFree(c->h_far);
+    c->h_far = nullptr;
+    if (c->ev_sort) (void)hipEventDestroy(c->ev_sort);
+    c->ev_sort = nullptr;
     for (auto& r : c->ranges) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -333,7 +339,8 @@ int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys, bool after_push) 
     const MoveArrays mv = move_arrays(c, s);
     if (local)
         HIPCHK(c, launch_sort_local(c->g, s.n, keys, s.sc_prev, s.perm, s.sc_off, c->scratch,
-                                    c->d_err, move ? &mv : nullptr, c->stream, &done));
+                                    c->d_err, move ? &mv : nullptr, c->h_far, c->ev_sort,
+                                    c->stream, &done));
     if (done && move) {
         s.cur = 1 - s.cur;
         s.pending = false;
@@ -1004,8 +1011,11 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         (e = dalloc(c, (void**)&c->d_nfar, 256)) != hipSuccess ||
         (e = dalloc(c, (void**)&c->far_n, 256)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc"));
-    if ((e = hipHostMalloc((void**)&c->h_err, 256, hipHostMallocDefault)) != hipSuccess)
+    if ((e = hipHostMalloc((void**)&c->h_err, 256, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&c->h_far, 64, hipHostMallocDefault)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipHostMalloc"));
+    if ((e = hipEventCreateWithFlags(&c->ev_sort, hipEventDisableTiming)) != hipSuccess)
+        return cfail(hip_fail(c, e, "hipEventCreate"));
     int64_t maxcap = 0;
     c->sp.resize(n_species);
     for (int s = 0; s < n_species; ++s) {

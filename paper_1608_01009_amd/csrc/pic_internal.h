@@ -204,15 +204,18 @@ struct MoveArrays {
 // The same order for a re-sort after a push (keys from that push, old_off the
 // supercell offsets of the current order), computed per supercell from its
 // 27 neighbours' particles when every particle's new supercell is one of the
-// 27 around its old one (periodic x, S^3 <= 64).  Synchronises the stream
-// once to read the number of particles that moved farther; *done is false
-// (nothing else written) when there are any, or the grid is not supported,
-// and launch_sort must be used instead.  With move (count > 0) the arrays are
-// also written in the new order (dst[i] = src[perm[i]]), staged per supercell
-// through LDS.
+// 27 around its old one (periodic x, S^3 <= 64).  The number of particles that
+// moved farther is copied to far_host (pinned host memory) and the rest of
+// the re-sort is queued behind that copy, each of its kernels doing nothing
+// when the number is not zero; the host then waits for the copy (event ev,
+// recorded here).  *done is false (nothing else written) when there are any,
+// or the grid is not supported, and launch_sort must be used instead.  With
+// move (count > 0) the arrays are also written in the new order
+// (dst[i] = src[perm[i]]), staged per supercell through LDS.
 hipError_t launch_sort_local(const Geom& g, int64_t n, const unsigned* keys, const int* old_off,
                              unsigned* perm, int* sc_off, void* scratch, unsigned* err,
-                             const MoveArrays* move, hipStream_t s, bool* done);
+                             const MoveArrays* move, unsigned* far_host, hipEvent_t ev,
+                             hipStream_t s, bool* done);
 // dst[i] = src[perm[i]] for the six state arrays and the ids.
 hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, const Parts& dst,
                           hipStream_t s);
@@ -221,8 +224,10 @@ hipError_t launch_permute_ids(int64_t n, const unsigned* perm, const int64_t* sr
 // dst[i] = src[perm[i]] for the arrays of mv, for a re-sort whose old order had
 // the supercell offsets old_off (each supercell's particles, mostly in one old
 // block, are staged through LDS); new_off: the offsets of the new order.
+// skip (device, may be null): nothing is done if *skip != 0 when the launch runs.
 hipError_t launch_staged_permute(const Geom& g, int64_t n, const unsigned* perm, const int* old_off,
-                                const int* new_off, const MoveArrays& mv, hipStream_t s);
+                                const int* new_off, const MoveArrays& mv, hipStream_t s,
+                                const unsigned* skip = nullptr);
 
 // Adjoint of one step (FP64).  launch_fdtd_adjoint: the transposed Yee update
 // in place on (lE, lB), writing lJ (the adjoint of the step's current).

@@ -81,9 +81,13 @@ __global__ void __launch_bounds__(kBlock) hist_kernel(const unsigned* key, int n
     for (int d = threadIdx.x; d < D; d += kBlock) hist[d * nblocks + blockIdx.x] = cnt[d];
 }
 
-// Exclusive scan, three phases over chunks of kTile elements.
+// Exclusive scan, three phases over chunks of kTile elements.  skip (when
+// not null): the launch does nothing if *skip != 0 (a decision taken on the
+// device by an earlier kernel of the stream).
 __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(const unsigned* in, int n,
-                                                             unsigned* sums) {
+                                                             unsigned* sums,
+                                                             const unsigned* skip) {
+    if (skip && *skip != 0u) return;
     __shared__ unsigned red[kBlock];
     const int b0 = blockIdx.x * kTile;
     unsigned s = 0;
@@ -118,7 +122,9 @@ __device__ unsigned block_exscan(unsigned v, unsigned* tmp) {
 // Single workgroup: exclusive scan of up to kTile chunk sums, in place.
 // Exclusive scan of the m block sums in one workgroup, kTile at a time with
 // a running carry (m may exceed kTile for more than 2^24 histogram entries).
-__global__ void __launch_bounds__(kBlock) scan_sums_kernel(unsigned* sums, int m) {
+__global__ void __launch_bounds__(kBlock) scan_sums_kernel(unsigned* sums, int m,
+                                                           const unsigned* skip) {
+    if (skip && *skip != 0u) return;
     __shared__ unsigned tmp[kBlock];
     __shared__ unsigned carry_s;
     unsigned carry = 0;
@@ -144,7 +150,9 @@ __global__ void __launch_bounds__(kBlock) scan_sums_kernel(unsigned* sums, int m
 }
 
 __global__ void __launch_bounds__(kBlock) scan_down_kernel(const unsigned* in, int n,
-                                                           const unsigned* sums, unsigned* out) {
+                                                           const unsigned* sums, unsigned* out,
+                                                           const unsigned* skip) {
+    if (skip && *skip != 0u) return;
     __shared__ unsigned tmp[kBlock];
     const int b0 = blockIdx.x * kTile;
     unsigned local[kRounds];
@@ -433,7 +441,8 @@ __device__ __forceinline__ void staged_move(const T* __restrict__ sp, T* __restr
 
 __global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
     const unsigned* __restrict__ perm, const int* __restrict__ old_off,
-    const int* __restrict__ new_off, MoveArrays mv) {
+    const int* __restrict__ new_off, MoveArrays mv, const unsigned* skip) {
+    if (skip && *skip != 0u) return;   // see scan_reduce_kernel
     __shared__ unsigned long long stage[kStage];
     const int s = xcd_range_block((int)blockIdx.x, (int)gridDim.x);
     const int n0 = new_off[s], n1 = new_off[s + 1];
@@ -692,7 +701,8 @@ __global__ void __launch_bounds__(kNbrMoveBlock) nbr_interleave_kernel(
     NbrGeom q, const unsigned* __restrict__ key, const int* __restrict__ old_off,
     const int* __restrict__ seg, const unsigned* __restrict__ list,
     const int* __restrict__ new_off, unsigned* __restrict__ tmp_j, unsigned* __restrict__ tmp_c,
-    unsigned* __restrict__ perm, unsigned* __restrict__ err) {
+    unsigned* __restrict__ perm, unsigned* __restrict__ err, const unsigned* skip) {
+    if (skip && *skip != 0u) return;   // see scan_reduce_kernel
     __shared__ unsigned lj[kNbrKeep];
     __shared__ unsigned char lc[kNbrKeep];
     __shared__ int k_src[27], k_start[27], k_cnt[27];
@@ -934,10 +944,12 @@ void radix_pass(const unsigned* kin, const unsigned* vin, unsigned* kout, unsign
     const int nsum = nblk(hn, kTile);
     hipLaunchKernelGGL((hist_kernel<BITS>), dim3(nb), dim3(kBlock), 0, s, kin, n, shift, nb,
                        sc.hist);
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn, sc.sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.sums, nsum);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn, sc.sums,
+                       (const unsigned*)nullptr);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.sums, nsum,
+                       (const unsigned*)nullptr);
     hipLaunchKernelGGL(scan_down_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.hist, hn, sc.sums,
-                       sc.offs);
+                       sc.offs, (const unsigned*)nullptr);
     hipLaunchKernelGGL((scatter_kernel<BITS>), dim3(nb), dim3(kBlock), 0, s, kin, vin, n, shift,
                        nb, sc.offs, kout, vout);
 }
@@ -1022,7 +1034,8 @@ hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const P
 
 hipError_t launch_sort_local(const Geom& g, int64_t n64, const unsigned* keys, const int* old_off,
                              unsigned* perm, int* sc_off, void* scratch, unsigned* err,
-                             const MoveArrays* move, hipStream_t s, bool* done) {
+                             const MoveArrays* move, unsigned* far_host, hipEvent_t ev,
+                             hipStream_t s, bool* done) {
     *done = false;
     const int n = (int)n64;
     const int S3 = g.S * g.S * g.S;
@@ -1049,27 +1062,32 @@ hipError_t launch_sort_local(const Geom& g, int64_t n64, const unsigned* keys, c
         hipLaunchKernelGGL(nbr_classify_kernel<false>, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys,
                            old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    unsigned far = 0;
-    if ((e = hipMemcpyAsync(&far, sc.nbr_far, sizeof(unsigned), hipMemcpyDeviceToHost, s)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
+    // The count of distant particles goes to the host, while the rest of the
+    // neighbourhood re-sort is queued behind it: each of its kernels does
+    // nothing when that count is not zero, and the host waits for the count
+    // only once they are queued, so the GPU does not idle through the wait.
+    if ((e = hipMemcpyAsync(far_host, sc.nbr_far, sizeof(unsigned), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipEventRecord(ev, s)) != hipSuccess)
         return e;
-    if (far != 0) return hipSuccess;   // the global sort takes over
+    const unsigned* gate = sc.nbr_far;
     const int m = g.nsc + 1;
     const int nsum = nblk(m, kTile);
     hipLaunchKernelGGL(scan_reduce_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.nbr_size, m,
-                       sc.nbr_sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.nbr_sums, nsum);
+                       sc.nbr_sums, gate);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sc.nbr_sums, nsum, gate);
     hipLaunchKernelGGL(scan_down_kernel, dim3(nsum), dim3(kBlock), 0, s, sc.nbr_size, m,
-                       sc.nbr_sums, (unsigned*)sc_off);
+                       sc.nbr_sums, (unsigned*)sc_off, gate);
     hipLaunchKernelGGL(nbr_interleave_kernel, dim3(g.nsc), dim3(kNbrMoveBlock), 0, s, q, keys,
                        old_off, (const int*)sc.nbr_cnt, (const unsigned*)sc.k1, (const int*)sc_off,
-                       sc.k0, sc.v0, perm, err);
+                       sc.k0, sc.v0, perm, err, gate);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (move && move->count > 0 &&
-        (e = launch_staged_permute(g, n, perm, old_off, sc_off, *move, s)) != hipSuccess)
+        (e = launch_staged_permute(g, n, perm, old_off, sc_off, *move, s, gate)) != hipSuccess)
         return e;
-    *done = true;
+    if ((e = hipEventSynchronize(ev)) != hipSuccess) return e;
+    // distant particles: the kernels above did nothing, the global sort takes over
+    *done = *(volatile unsigned*)far_host == 0u;
     return hipSuccess;
 }
 
@@ -1082,11 +1100,12 @@ hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, con
 }
 
 hipError_t launch_staged_permute(const Geom& g, int64_t n, const unsigned* perm, const int* old_off,
-                                const int* new_off, const MoveArrays& mv, hipStream_t s) {
+                                const int* new_off, const MoveArrays& mv, hipStream_t s,
+                                const unsigned* skip) {
     if (n <= 0 || g.nsc <= 0 || mv.count == 0) return hipSuccess;
     if (mv.count > 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(staged_permute_kernel, dim3(g.nsc), dim3(kStageBlock), 0, s, perm, old_off,
-                       new_off, mv);
+                       new_off, mv, skip);
     return hipGetLastError();
 }
 
