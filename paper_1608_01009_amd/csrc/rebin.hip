@@ -393,11 +393,13 @@ constexpr int kStage = 4096;   // 8-byte values per array held in LDS (or 8192 4
 // the source is in the staged part.  The loads of a thread's elements are
 // issued together (KB per round) before their values are used, so that their
 // latencies overlap.
+constexpr int kStageKB = 8;
+
 template <class T, int CAP>
 __device__ __forceinline__ void staged_move(const T* __restrict__ sp, T* __restrict__ dp,
                                             T* stage, const unsigned* __restrict__ perm, int o0,
                                             int ob, int n0, int n1) {
-    constexpr int KB = 8;
+    constexpr int KB = kStageKB;
     const unsigned cap = (unsigned)min(ob, CAP);
     for (int b = 0; b < (int)cap; b += KB * kStageBlock) {
         T v[KB];
@@ -439,6 +441,47 @@ __device__ __forceinline__ void staged_move(const T* __restrict__ sp, T* __restr
     }
 }
 
+// The same for a new block of at most kStageKB * kStageBlock elements whose
+// sources jj (perm[n0 + k * kStageBlock + thread]) the caller loaded once for
+// all the arrays.
+template <class T, int CAP>
+__device__ __forceinline__ void staged_move_pre(const T* __restrict__ sp, T* __restrict__ dp,
+                                                T* stage, const unsigned (&jj)[kStageKB], int o0,
+                                                int ob, int n0, int n1) {
+    constexpr int KB = kStageKB;
+    const unsigned cap = (unsigned)min(ob, CAP);
+    for (int b = 0; b < (int)cap; b += KB * kStageBlock) {
+        T v[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const unsigned t = (unsigned)(b + k * kStageBlock) + threadIdx.x;
+            if (t < cap) v[k] = sp[o0 + (int)t];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const unsigned t = (unsigned)(b + k * kStageBlock) + threadIdx.x;
+            if (t < cap) stage[t] = v[k];
+        }
+    }
+    __syncthreads();
+    T v[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const unsigned u = jj[k] - (unsigned)o0;
+        if (u >= cap) v[k] = sp[jj[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const unsigned u = jj[k] - (unsigned)o0;
+        if (u < cap) v[k] = stage[u];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int i = n0 + k * kStageBlock + (int)threadIdx.x;
+        if (i < n1) dp[i] = v[k];
+    }
+}
+
 __global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
     const unsigned* __restrict__ perm, const int* __restrict__ old_off,
     const int* __restrict__ new_off, MoveArrays mv, const unsigned* skip) {
@@ -449,6 +492,28 @@ __global__ void __launch_bounds__(kStageBlock) staged_permute_kernel(
     if (n0 >= n1) return;
     const int o0 = old_off[s];
     const int ob = old_off[s + 1] - o0;
+    if (n1 - n0 <= kStageKB * kStageBlock) {
+        // the order of the block read once for every array
+        unsigned jj[kStageKB];
+#pragma unroll
+        for (int k = 0; k < kStageKB; ++k) {
+            const int i = n0 + k * kStageBlock + (int)threadIdx.x;
+            jj[k] = i < n1 ? perm[i] : (unsigned)o0;
+        }
+#pragma unroll 1
+        for (int a = 0; a < mv.count; ++a) {
+            if (mv.bytes[a] == 8)
+                staged_move_pre<unsigned long long, kStage>(
+                    (const unsigned long long*)mv.src[a], (unsigned long long*)mv.dst[a], stage,
+                    jj, o0, ob, n0, n1);
+            else
+                staged_move_pre<unsigned, 2 * kStage>((const unsigned*)mv.src[a],
+                                                      (unsigned*)mv.dst[a], (unsigned*)stage, jj,
+                                                      o0, ob, n0, n1);
+            __syncthreads();
+        }
+        return;
+    }
 #pragma unroll 1
     for (int a = 0; a < mv.count; ++a) {
         if (mv.bytes[a] == 8)
