@@ -20,6 +20,19 @@ KEYS = ("x", "y", "z", "ux", "uy", "uz", "id")
 REL_TOL = 1e-12
 
 
+def dense_beam_workload():
+    """6,400 particles per 4^3 supercell on 4 x 2 x 2 supercells (dense: a
+    re-sort moves the data), every 32nd particle at about 0.99 c along x: it
+    moves about 5.7 cells in the 20 steps before the first re-sort, and those
+    starting in the last part of their supercell end two supercells on."""
+    from paper_1608_01009_amd import workloads as W
+    wl = W.scaled(2, (16, 8, 8), 100, seed=90)
+    sp = wl.species[0]
+    rng = np.random.default_rng(91)
+    sp.ux[5::32] = 6.0 + rng.random(len(sp.ux[5::32]))
+    return wl
+
+
 def log(*a):
     print(*a, flush=True)
     sys.stdout.flush()

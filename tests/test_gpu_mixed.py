@@ -20,7 +20,7 @@ import pytest
 from paper_1608_01009_amd import pic
 from paper_1608_01009_amd import workloads as W
 
-from gpu_parity_util import KEYS, log, read_state
+from gpu_parity_util import KEYS, dense_beam_workload, log, read_state
 
 from gpu_layout import LayoutOracle
 
@@ -302,6 +302,13 @@ def test_mixed_dense_supercells_resort(n, ppc):
     # case beyond its buffers); steps 19 (ends with the re-sort), 20, 21
     wl = W.scaled(2, n, ppc, seed=170 + ppc)
     _run(wl, [19, 20, 21], _against_mixed_oracle)
+
+
+def test_mixed_dense_resort_with_particles_beyond_the_neighbouring_supercells():
+    # the dense beam workload of test_gpu_parity (which checks that particles
+    # end two supercells on): the neighbourhood re-sort gives way to the global
+    # sort, whose order the push after it applies with the staged permutation
+    _run(dense_beam_workload(), [19, 20, 21], _against_mixed_oracle)
 
 
 def test_mixed_resort_with_particles_beyond_the_neighbouring_supercells():

@@ -14,7 +14,8 @@ import pytest
 from paper_1608_01009_amd import pic
 from paper_1608_01009_amd import workloads as W
 
-from gpu_parity_util import KEYS, compare, log, one_step_parity, oracle_for, read_state
+from gpu_parity_util import (KEYS, compare, dense_beam_workload, log, one_step_parity,
+                             oracle_for, read_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -154,6 +155,25 @@ def test_resort_with_particles_beyond_the_neighbouring_supercells():
     log(f"  particles beyond the neighbouring supercells at the first re-sort: {moved}")
     assert moved > 0
     one_step_parity(wl, [9, 10, 19, 20])[1].close()
+
+
+def test_dense_resort_with_particles_beyond_the_neighbouring_supercells():
+    # the neighbourhood re-sort's queued kernels do nothing (the count of
+    # distant particles is not zero), the global sort takes over, and the push
+    # after it starts with the staged permutation of that order; steps 19 (ends
+    # with the re-sort), 20 and 21 against the oracle
+    wl = dense_beam_workload()
+    sim = pic.Simulation.from_workload(wl)
+    a = sim.particles(0)
+    sim.step(20)
+    b = sim.particles(0)
+    sim.close()
+    ia, ib = np.argsort(a["id"][:a["n"]]), np.argsort(b["id"][:b["n"]])
+    d = (np.floor(b["x"][ib] / 4.0) - np.floor(a["x"][ia] / 4.0)) % 4
+    moved = int(np.sum(d == 2))
+    log(f"  dense: particles two supercells on at the first re-sort: {moved}")
+    assert moved > 0
+    one_step_parity(wl, [19, 20, 21])[1].close()
 
 
 def test_two_dense_species_resort():
