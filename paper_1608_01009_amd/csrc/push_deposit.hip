@@ -718,7 +718,10 @@ __global__ void __launch_bounds__(kBlock) far_kernel(const PDArgs a) {
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const double L[3] = {(double)nx, (double)ny, (double)nz};
     unsigned long long cnt = 0;
-    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    // queue entry i goes to workgroup i mod gridDim: a short queue (the usual
+    // case) spreads one particle per workgroup over the CUs instead of
+    // filling the waves of the first workgroup
+    for (unsigned i = threadIdx.x * gridDim.x + blockIdx.x; i < n; i += gridDim.x * kBlock) {
         const int ip = a.far_q[i];
         const unsigned j = a.perm ? a.perm[ip] : (unsigned)ip;
         double x0[3] = {a.src.x[j], a.src.y[j], a.src.z[j]};

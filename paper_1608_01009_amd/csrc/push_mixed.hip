@@ -655,7 +655,10 @@ __global__ void __launch_bounds__(kBlock) far_mixed_kernel(const MArgs a) {
     const Geom& g = a.g;
     const int nn[3] = {g.n[0], g.n[1], g.n[2]};
     unsigned long long cnt = 0;
-    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    // queue entry i goes to workgroup i mod gridDim: a short queue (the usual
+    // case) spreads one particle per workgroup over the CUs instead of
+    // filling the waves of the first workgroup
+    for (unsigned i = threadIdx.x * gridDim.x + blockIdx.x; i < n; i += gridDim.x * kBlock) {
         const int ip = a.far_q[i];
         const unsigned j = a.perm ? a.perm[ip] : (unsigned)ip;
         int c[3];
