@@ -105,8 +105,9 @@ struct pic_ctx {
     int far_phase = 0;
     int pair_phase = 0;            // counters far_n[4..7] of the two-species launch
     unsigned* h_err = nullptr;
-    unsigned* h_far = nullptr;     // pinned: distant-particle count of the last re-sort
-    hipEvent_t ev_sort = nullptr;  // recorded after that count's copy
+    unsigned* h_far = nullptr;     // pinned, coherent: raised by a re-sort's classification
+    unsigned* d_far = nullptr;     // (distant particles); d_far is its device address
+    hipEvent_t ev_sort = nullptr;  // recorded after that classification
     double* rho = nullptr;
     double* tmp = nullptr;
     double* G0 = nullptr;
@@ -331,15 +332,14 @@ MoveArrays move_arrays(const pic_ctx* c, const SpeciesState& s) {
 // moves the data into the new order.  Otherwise (a load, or the global sort)
 // the data move later: with the next push, or by the staged permutation.
 int do_sort(pic_ctx* c, SpeciesState& s, const unsigned* keys, bool after_push) {
-    HIPCHK(c, hipMemcpyAsync(s.sc_prev, s.sc_off, (size_t)(c->g.nsc + 1) * sizeof(int),
-                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_resort_prep(c->g, s.n, s.sc_off, s.sc_prev, c->scratch, c->stream));
     bool done = false;
     const bool local = after_push && keys && !c->g.absorb_x;
     const bool move = local && s.n >= (int64_t)kStagedPermuteMin * c->g.nsc;
     const MoveArrays mv = move_arrays(c, s);
     if (local)
         HIPCHK(c, launch_sort_local(c->g, s.n, keys, s.sc_prev, s.perm, s.sc_off, c->scratch,
-                                    c->d_err, move ? &mv : nullptr, c->h_far, c->ev_sort,
+                                    c->d_err, move ? &mv : nullptr, c->h_far, c->d_far, c->ev_sort,
                                     c->stream, &done));
     if (done && move) {
         s.cur = 1 - s.cur;
@@ -1012,7 +1012,9 @@ int pic_create(const pic_grid_t* grid, const double dx[3], double dt,
         (e = dalloc(c, (void**)&c->far_n, 256)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipMalloc"));
     if ((e = hipHostMalloc((void**)&c->h_err, 256, hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&c->h_far, 64, hipHostMallocDefault)) != hipSuccess)
+        (e = hipHostMalloc((void**)&c->h_far, 64, hipHostMallocMapped | hipHostMallocCoherent)) !=
+            hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&c->d_far, c->h_far, 0)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipHostMalloc"));
     if ((e = hipEventCreateWithFlags(&c->ev_sort, hipEventDisableTiming)) != hipSuccess)
         return cfail(hip_fail(c, e, "hipEventCreate"));

@@ -204,18 +204,25 @@ struct MoveArrays {
 // The same order for a re-sort after a push (keys from that push, old_off the
 // supercell offsets of the current order), computed per supercell from its
 // 27 neighbours' particles when every particle's new supercell is one of the
-// 27 around its old one (periodic x, S^3 <= 64).  The number of particles that
-// moved farther is copied to far_host (pinned host memory) and the rest of
-// the re-sort is queued behind that copy, each of its kernels doing nothing
-// when the number is not zero; the host then waits for the copy (event ev,
-// recorded here).  *done is false (nothing else written) when there are any,
+// 27 around its old one (periodic x, S^3 <= 64), after launch_resort_prep.
+// The classification raises *far_host (coherent pinned host memory, cleared
+// here; far_dev is its device address) if
+// any particle moved farther, and the rest of the re-sort is queued behind it,
+// each of its kernels doing nothing in that case; the host then waits for the
+// classification (event ev, recorded here).  *done is false (nothing else
+// written) when there are any,
 // or the grid is not supported, and launch_sort must be used instead.  With
 // move (count > 0) the arrays are also written in the new order
 // (dst[i] = src[perm[i]]), staged per supercell through LDS.
+// Start of every re-sort: sc_prev = sc_off (the supercell offsets of the
+// order before it) and the neighbourhood re-sort's counters in scratch
+// cleared, in one launch.
+hipError_t launch_resort_prep(const Geom& g, int64_t n, const int* sc_off, int* sc_prev,
+                              void* scratch, hipStream_t s);
 hipError_t launch_sort_local(const Geom& g, int64_t n, const unsigned* keys, const int* old_off,
                              unsigned* perm, int* sc_off, void* scratch, unsigned* err,
-                             const MoveArrays* move, unsigned* far_host, hipEvent_t ev,
-                             hipStream_t s, bool* done);
+                             const MoveArrays* move, unsigned* far_host, unsigned* far_dev,
+                             hipEvent_t ev, hipStream_t s, bool* done);
 // dst[i] = src[perm[i]] for the six state arrays and the ids.
 hipError_t launch_permute(int64_t n, const unsigned* perm, const Parts& src, const Parts& dst,
                           hipStream_t s);

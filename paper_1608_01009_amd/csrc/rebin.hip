@@ -641,7 +641,7 @@ template <bool POW2>
 __global__ void __launch_bounds__(kNbrBlock) nbr_classify_kernel(
     NbrGeom q, const unsigned* __restrict__ key, const int* __restrict__ old_off,
     int* __restrict__ cnt_out, unsigned* __restrict__ list, unsigned* __restrict__ size,
-    unsigned* __restrict__ distant) {
+    unsigned* __restrict__ distant, unsigned* host_flag) {
     __shared__ unsigned char dirs[kNbrKeepDirs];
     __shared__ unsigned wcnt[kNbrWaves][kNbrStride];
     __shared__ unsigned tot[kNbrStride];
@@ -709,7 +709,11 @@ __global__ void __launch_bounds__(kNbrBlock) nbr_classify_kernel(
             r += tot[d];
         }
         seg[kNbrDirs] = r;
-        if (tot[kNbrDistant] > 0) atomicAdd(distant, tot[kNbrDistant]);
+        if (tot[kNbrDistant] > 0) {
+            atomicAdd(distant, tot[kNbrDistant]);
+            // and a flag for the host, written through to its pinned memory
+            __hip_atomic_store(host_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
     __syncthreads();
     // segment starts in the block per direction (and the block size last)
@@ -1097,10 +1101,36 @@ hipError_t launch_sort(const Geom& g, int64_t n64, const unsigned* keys, const P
     return hipGetLastError();
 }
 
+namespace {
+
+// Start of a re-sort: the current supercell offsets copied as the old ones,
+// and the neighbourhood re-sort's sizes and distant count cleared.
+__global__ void __launch_bounds__(kBlock) resort_prep_kernel(const int* __restrict__ cur,
+                                                             int* __restrict__ prev, int m_copy,
+                                                             unsigned* __restrict__ zero,
+                                                             int m_zero) {
+    const int m = m_copy > m_zero ? m_copy : m_zero;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+        if (i < m_copy) prev[i] = cur[i];
+        if (i < m_zero) zero[i] = 0u;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_resort_prep(const Geom& g, int64_t n, const int* sc_off, int* sc_prev,
+                              void* scratch, hipStream_t s) {
+    Scratch sc = carve(scratch, n, g.nsc);
+    const int m = g.nsc + 2;
+    hipLaunchKernelGGL(resort_prep_kernel, dim3(nblk(m, kBlock)), dim3(kBlock), 0, s, sc_off,
+                       sc_prev, g.nsc + 1, sc.nbr_size, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort_local(const Geom& g, int64_t n64, const unsigned* keys, const int* old_off,
                              unsigned* perm, int* sc_off, void* scratch, unsigned* err,
-                             const MoveArrays* move, unsigned* far_host, hipEvent_t ev,
-                             hipStream_t s, bool* done) {
+                             const MoveArrays* move, unsigned* far_host, unsigned* far_dev,
+                             hipEvent_t ev, hipStream_t s, bool* done) {
     *done = false;
     const int n = (int)n64;
     const int S3 = g.S * g.S * g.S;
@@ -1117,24 +1147,23 @@ hipError_t launch_sort_local(const Geom& g, int64_t n64, const unsigned* keys, c
     q.sh1 = pow2 ? __builtin_ctz((unsigned)g.ns[1]) : -1;
     q.rns0 = 1.0f / (float)g.ns[0];
     q.rns1 = 1.0f / (float)g.ns[1];
-    // the sizes (summed by the classification) and the distant count
-    hipError_t e = hipMemsetAsync(sc.nbr_size, 0, (size_t)(g.nsc + 2) * sizeof(unsigned), s);
-    if (e != hipSuccess) return e;
+    // the sizes and the distant count were cleared by launch_resort_prep; the
+    // classification raises *far_host (pinned host memory) if any particle is
+    // distant
+    *(volatile unsigned*)far_host = 0u;
+    hipError_t e;
     if (pow2)
         hipLaunchKernelGGL(nbr_classify_kernel<true>, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys,
-                           old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
+                           old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far, far_dev);
     else
         hipLaunchKernelGGL(nbr_classify_kernel<false>, dim3(g.nsc), dim3(kNbrBlock), 0, s, q, keys,
-                           old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far);
+                           old_off, sc.nbr_cnt, sc.k1, sc.nbr_size, sc.nbr_far, far_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // The count of distant particles goes to the host, while the rest of the
-    // neighbourhood re-sort is queued behind it: each of its kernels does
-    // nothing when that count is not zero, and the host waits for the count
+    // The rest of the neighbourhood re-sort is queued behind the
+    // classification: each of its kernels does nothing when the distant count
+    // is not zero, and the host waits for the classification (and its flag)
     // only once they are queued, so the GPU does not idle through the wait.
-    if ((e = hipMemcpyAsync(far_host, sc.nbr_far, sizeof(unsigned), hipMemcpyDeviceToHost,
-                            s)) != hipSuccess ||
-        (e = hipEventRecord(ev, s)) != hipSuccess)
-        return e;
+    if ((e = hipEventRecord(ev, s)) != hipSuccess) return e;
     const unsigned* gate = sc.nbr_far;
     const int m = g.nsc + 1;
     const int nsum = nblk(m, kTile);
