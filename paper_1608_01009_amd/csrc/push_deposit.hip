@@ -276,10 +276,64 @@ __device__ __forceinline__ double interp_oct(const Oct& o, double fx, double fy,
     return __fma_rn(fz, r1 - r0, r0);
 }
 
+// The same from a tile of x-pairs (value, difference to x + 1): four 16-byte
+// reads per component, and the x lerps take the stored difference.
+typedef double vd2 __attribute__((ext_vector_type(2)));
+struct Quad {
+    vd2 p[4];
+};
+
+template <int PY, int PZ>
+__device__ __forceinline__ Quad ld_quad(const double* eb, int base) {
+    asm volatile("" : "+v"(base));
+    typedef __attribute__((address_space(3))) const volatile vd2 lds_vd2;
+    const lds_vd2* p = (const lds_vd2*)(eb + base);
+    Quad o;
+    o.p[0] = p[0];
+    o.p[1] = p[PY / 2];
+    o.p[2] = p[PZ / 2];
+    o.p[3] = p[(PZ + PY) / 2];
+    return o;
+}
+
+__device__ __forceinline__ double interp_quad(const Quad& o, double fx, double fy, double fz) {
+#pragma clang fp contract(off)
+    const double q00 = __fma_rn(fx, o.p[0].y, o.p[0].x);
+    const double q10 = __fma_rn(fx, o.p[1].y, o.p[1].x);
+    const double q01 = __fma_rn(fx, o.p[2].y, o.p[2].x);
+    const double q11 = __fma_rn(fx, o.p[3].y, o.p[3].x);
+    const double r0 = __fma_rn(fy, q10 - q00, q00);
+    const double r1 = __fma_rn(fy, q11 - q01, q01);
+    return __fma_rn(fz, r1 - r0, r0);
+}
+
+template <int PY, int PZ, int CS>
+__device__ __forceinline__ void gather_tile_pairs(const double* eb, const Stencil& st,
+                                                  const int off[3], double E[3], double Bf[3]) {
+    const int x0 = 2 * (st.i0[0] + off[0]), y0 = st.i0[1] + off[1], z0 = st.i0[2] + off[2];
+    const int xh = 2 * (st.ih[0] + off[0]), yh = st.ih[1] + off[1], zh = st.ih[2] + off[2];
+    Quad a = ld_quad<PY, PZ>(eb, 0 * CS + xh + PY * y0 + PZ * z0);
+    Quad b = ld_quad<PY, PZ>(eb, 1 * CS + x0 + PY * yh + PZ * z0);
+    E[0] = interp_quad(a, st.fh[0], st.f0[1], st.f0[2]);
+    a = ld_quad<PY, PZ>(eb, 2 * CS + x0 + PY * y0 + PZ * zh);
+    E[1] = interp_quad(b, st.f0[0], st.fh[1], st.f0[2]);
+    b = ld_quad<PY, PZ>(eb, 3 * CS + x0 + PY * yh + PZ * zh);
+    E[2] = interp_quad(a, st.f0[0], st.f0[1], st.fh[2]);
+    a = ld_quad<PY, PZ>(eb, 4 * CS + xh + PY * y0 + PZ * zh);
+    Bf[0] = interp_quad(b, st.f0[0], st.fh[1], st.fh[2]);
+    b = ld_quad<PY, PZ>(eb, 5 * CS + xh + PY * yh + PZ * z0);
+    Bf[1] = interp_quad(a, st.fh[0], st.f0[1], st.fh[2]);
+    Bf[2] = interp_quad(b, st.fh[0], st.fh[1], st.f0[2]);
+}
+
 template <class EL>
 __device__ __forceinline__ void gather_tile(const double* eb, const Stencil& st, const int off[3],
                                             double E[3], double Bf[3]) {
     constexpr int PY = EL::PY, PZ = EL::PZ, CS = EL::CS;
+    if constexpr (EL::kPair) {
+        gather_tile_pairs<PY, PZ, CS>(eb, st, off, E, Bf);
+        return;
+    }
     const int x0 = st.i0[0] + off[0], y0 = st.i0[1] + off[1], z0 = st.i0[2] + off[2];
     const int xh = st.ih[0] + off[0], yh = st.ih[1] + off[1], zh = st.ih[2] + off[2];
     // Yee stagger per component: Ex (h,0,0) Ey (0,h,0) Ez (0,0,h)
@@ -319,16 +373,21 @@ __device__ __forceinline__ void vb_single(const double x0[3], const double x1[3]
     vb_cell(a, b, jc, add);
 }
 
-// Layout of the E/B tile in LDS: node (tx, ty, tz) of component c lives at
-// c * CS + tx + PY * ty + PZ * tz.  For S = 4 the plane pitch is padded from
-// 64 to 68 doubles, which spreads the stencils of the lanes of a round (two
-// z-layers of the supercell per half wave, each lane shifted by the
-// component's stagger) over more LDS banks.
-template <int S, int H>
+// Layout of the E/B tile in LDS.  PAIR: x-pairs; for node (tx, ty, tz) of
+// component c with tx < T - 1, the value at c * CS + 2 tx + PY * ty + PZ * tz
+// and, beside it, the difference to the next node in x (what the first lerp
+// of the interpolation subtracts, formed once per node instead of once per
+// particle; the same FP64 subtraction, so the result is unchanged): one
+// 16-byte read per pair.  Otherwise node (tx, ty, tz) at c * CS + tx + PY * ty
+// + PZ * tz.  For S = 4 the plane pitch is padded by 4 doubles, which spreads
+// the stencils of the lanes of a round (two z-layers of the supercell per half
+// wave, each lane shifted by the component's stagger) over more LDS banks.
+template <int S, int H, bool PAIR>
 struct EBLayout {
     static constexpr int T = S + 2 * H + 2;
-    static constexpr int PY = T;
-    static constexpr int PZ = (S == 4) ? T * T + 4 : T * T;
+    static constexpr bool kPair = PAIR;
+    static constexpr int PY = PAIR ? 2 * (T - 1) : T;
+    static constexpr int PZ = (S == 4) ? PY * T + 4 : PY * T;
     static constexpr int CS = PZ * T;  // doubles per component
 };
 
@@ -368,7 +427,9 @@ template <int S, int H, bool GATHER, bool DET, bool ABS, int NSP>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 push_deposit_kernel(const PDMulti<NSP> m) {
     const PDArgs& a = m.s[0];   // shared: geometry, fields, J, det, error word
-    using EL = EBLayout<S, H>;
+    // x-pairs for one species without DET: with DET's larger J tile they would
+    // leave one workgroup per CU, and the two-species kernels spill with them
+    using EL = EBLayout<S, H, !DET && NSP == 1>;
     constexpr int T = EL::T;           // E/B tile edge in nodes
     constexpr int T2 = T * T, T3 = T2 * T;
     using JL = JLayout<S, H>;
@@ -376,7 +437,7 @@ push_deposit_kernel(const PDMulti<NSP> m) {
     constexpr int PY = JL::PY, PZ = JL::PZ, JC = JL::JC;
     constexpr int kWaves = kBlock / 64;
     constexpr int QCAP = 28;           // queued cell-crossing particles per wave
-    __shared__ double eb[6 * EL::CS];
+    __shared__ __attribute__((aligned(16))) double eb[6 * EL::CS];
     // J tile: FP64 sums, or (DET) 64-bit hi sums followed by 32-bit lo sums
     constexpr int JT_BYTES = DET ? 3 * JC * 12 : 3 * JC * 8;
     __shared__ __attribute__((aligned(16))) unsigned char jraw[JT_BYTES];
@@ -489,13 +550,31 @@ push_deposit_kernel(const PDMulti<NSP> m) {
         const int r = (int)threadIdx.x + i * kBlock;
         if (r < T3) {
             const int tz = r / T2, ty = (r / T) % T, tx = r % T;
-            const int li = tx + EL::PY * ty + EL::PZ * tz;
+            // x-pairs: the values first (the last node of a row in the
+            // difference slot of the pair before it), then the differences
+            const int lx = !EL::kPair ? tx : (tx < T - 1 ? 2 * tx : 2 * T - 3);
+            const int li = lx + EL::PY * ty + EL::PZ * tz;
 #pragma unroll
             for (int c = 0; c < 6; ++c) eb[c * EL::CS + li] = tv[i][c];
         }
     }
     for (int t = threadIdx.x; t < JT_BYTES / 4; t += kBlock) ((int*)jraw)[t] = 0;
     __syncthreads();
+    if constexpr (EL::kPair) {
+#pragma unroll
+        for (int i = 0; i < TN; ++i) {
+            const int r = (int)threadIdx.x + i * kBlock;
+            const int tz = r / T2, ty = (r / T) % T, tx = r % T;
+            if (r < T3 && tx < T - 1) {
+                const int li = 2 * tx + EL::PY * ty + EL::PZ * tz;
+                const int ln = tx < T - 2 ? li + 2 : li + 1;
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    eb[c * EL::CS + li + 1] = eb[c * EL::CS + ln] - tv[i][c];
+            }
+        }
+        __syncthreads();
+    }
 
     const double L[3] = {(double)nx, (double)ny, (double)nz};
     const int nn[3] = {nx, ny, nz};
@@ -853,7 +932,8 @@ hipError_t launch_sh_pair(const PDArgs& a0, const PDArgs& a1, hipStream_t s) {
 
 template <int S, int H>
 constexpr int lds_bytes_sh(bool det) {
-    return (6 * EBLayout<S, H>::CS + (kBlock / 64) * 6 * 28) * (int)sizeof(double) +
+    return (6 * (det ? EBLayout<S, H, false>::CS : EBLayout<S, H, true>::CS) +
+            (kBlock / 64) * 6 * 28) * (int)sizeof(double) +
            3 * JLayout<S, H>::JC * (det ? 12 : 8);
 }
 

@@ -71,17 +71,20 @@ struct MArgs {
     DetJ det;               // deterministic mode (hi[0] == nullptr: off)
 };
 
-// LDS layouts: FP32 E/B tile, node (tx, ty, tz) of component c at
-// c * ECS + tx + EPY ty + EPZ tz; FP64 J tile, node of component d at
-// d * JC + tx + JPY ty + JPZ tz.  For S = 4, h = 1 the pitches are those
-// measured cheapest for the access pattern of a round of particles (the
-// E/B plane pitch padded from 64 to 68; the J pitches 12 / 112 put a half
-// wave of 32 cells on 32 distinct bank pairs).
+// LDS layouts: FP32 E/B tile of x-pairs: for node (tx, ty, tz) of component
+// c with tx < T - 1, the value at 2 tx + EPY ty + EPZ tz + c * ECS and, beside
+// it, the difference to the next node in x (what the first lerp of the CIC
+// interpolation subtracts, formed once per node instead of once per
+// particle; the same FP32 subtraction, so the result is unchanged); FP64 J
+// tile, node of component d at d * JC + tx + JPY ty + JPZ tz.  For S = 4,
+// h = 1 the pitches are those measured cheapest for the access pattern of a
+// round of particles (the E/B plane pitch padded by 4 floats; the J pitches
+// 12 / 112 put a half wave of 32 cells on 32 distinct bank pairs).
 template <int S, int H>
 struct MLayout {
     static constexpr int T = S + 2 * H + 2;
-    static constexpr int EPY = T;
-    static constexpr int EPZ = (S == 4) ? T * T + 4 : T * T;
+    static constexpr int EPY = 2 * (T - 1);
+    static constexpr int EPZ = (S == 4) ? EPY * T + 4 : EPY * T;
     static constexpr int ECS = EPZ * T;
     static constexpr int TJ = S + 2 * H + 3;
     static constexpr int JPY = (S == 4 && H == 1) ? 12 : TJ;
@@ -102,27 +105,10 @@ __device__ __forceinline__ void half_stencil(int c, float o, int& ih, float& fh)
     fh = up ? o - 0.5f : o + 0.5f;
 }
 
-// Eight lattice values of one component from the LDS tile (single reads).
+// Eight lattice values of one component (far movers' global gather).
 struct Oct8 {
     float v[8];
 };
-
-template <int PY, int PZ>
-__device__ __forceinline__ Oct8 ld_oct8(const float* eb, int base) {
-    asm volatile("" : "+v"(base));
-    typedef __attribute__((address_space(3))) const volatile float lds_float;
-    const lds_float* p = (const lds_float*)(eb + base);
-    Oct8 o;
-    o.v[0] = p[0];
-    o.v[1] = p[1];
-    o.v[2] = p[PY];
-    o.v[3] = p[PY + 1];
-    o.v[4] = p[PZ];
-    o.v[5] = p[PZ + 1];
-    o.v[6] = p[PZ + PY];
-    o.v[7] = p[PZ + PY + 1];
-    return o;
-}
 
 __device__ __forceinline__ float interp8(const Oct8& o, float fx, float fy, float fz) {
 #pragma clang fp contract(off)
@@ -130,6 +116,38 @@ __device__ __forceinline__ float interp8(const Oct8& o, float fx, float fy, floa
     const float q10 = lerpf(o.v[2], o.v[3], fx);
     const float q01 = lerpf(o.v[4], o.v[5], fx);
     const float q11 = lerpf(o.v[6], o.v[7], fx);
+    const float r0 = lerpf(q00, q10, fy);
+    const float r1 = lerpf(q01, q11, fy);
+    return lerpf(r0, r1, fz);
+}
+
+// The four x-pairs (value, difference to x + 1) of one component's stencil
+// from the LDS tile: one 8-byte read each.
+typedef float vf2 __attribute__((ext_vector_type(2)));
+struct Pair4 {
+    vf2 p[4];
+};
+
+template <int PY, int PZ>
+__device__ __forceinline__ Pair4 ld_pair4(const float* eb, int base) {
+    asm volatile("" : "+v"(base));
+    typedef __attribute__((address_space(3))) const volatile vf2 lds_float2;
+    const lds_float2* p = (const lds_float2*)(eb + base);
+    Pair4 o;
+    o.p[0] = p[0];
+    o.p[1] = p[PY / 2];
+    o.p[2] = p[PZ / 2];
+    o.p[3] = p[(PZ + PY) / 2];
+    return o;
+}
+
+// interp8 on x-pairs: the x lerps take the stored difference.
+__device__ __forceinline__ float interp_pairs(const Pair4& o, float fx, float fy, float fz) {
+#pragma clang fp contract(off)
+    const float q00 = __fmaf_rn(fx, o.p[0].y, o.p[0].x);
+    const float q10 = __fmaf_rn(fx, o.p[1].y, o.p[1].x);
+    const float q01 = __fmaf_rn(fx, o.p[2].y, o.p[2].x);
+    const float q11 = __fmaf_rn(fx, o.p[3].y, o.p[3].x);
     const float r0 = lerpf(q00, q10, fy);
     const float r1 = lerpf(q01, q11, fy);
     return lerpf(r0, r1, fz);
@@ -157,20 +175,20 @@ template <class L>
 __device__ __forceinline__ void gather_tile_m(const float* eb, const StencilM& st,
                                               const int off[3], float E[3], float B[3]) {
     constexpr int PY = L::EPY, PZ = L::EPZ, CS = L::ECS;
-    const int x0 = st.i0[0] + off[0], y0 = st.i0[1] + off[1], z0 = st.i0[2] + off[2];
-    const int xh = st.ih[0] + off[0], yh = st.ih[1] + off[1], zh = st.ih[2] + off[2];
-    Oct8 a = ld_oct8<PY, PZ>(eb, 0 * CS + xh + PY * y0 + PZ * z0);
-    Oct8 b = ld_oct8<PY, PZ>(eb, 1 * CS + x0 + PY * yh + PZ * z0);
-    E[0] = interp8(a, st.fh[0], st.f0[1], st.f0[2]);
-    a = ld_oct8<PY, PZ>(eb, 2 * CS + x0 + PY * y0 + PZ * zh);
-    E[1] = interp8(b, st.f0[0], st.fh[1], st.f0[2]);
-    b = ld_oct8<PY, PZ>(eb, 3 * CS + x0 + PY * yh + PZ * zh);
-    E[2] = interp8(a, st.f0[0], st.f0[1], st.fh[2]);
-    a = ld_oct8<PY, PZ>(eb, 4 * CS + xh + PY * y0 + PZ * zh);
-    B[0] = interp8(b, st.f0[0], st.fh[1], st.fh[2]);
-    b = ld_oct8<PY, PZ>(eb, 5 * CS + xh + PY * yh + PZ * z0);
-    B[1] = interp8(a, st.fh[0], st.f0[1], st.fh[2]);
-    B[2] = interp8(b, st.fh[0], st.fh[1], st.f0[2]);
+    const int x0 = 2 * (st.i0[0] + off[0]), y0 = st.i0[1] + off[1], z0 = st.i0[2] + off[2];
+    const int xh = 2 * (st.ih[0] + off[0]), yh = st.ih[1] + off[1], zh = st.ih[2] + off[2];
+    Pair4 a = ld_pair4<PY, PZ>(eb, 0 * CS + xh + PY * y0 + PZ * z0);
+    Pair4 b = ld_pair4<PY, PZ>(eb, 1 * CS + x0 + PY * yh + PZ * z0);
+    E[0] = interp_pairs(a, st.fh[0], st.f0[1], st.f0[2]);
+    a = ld_pair4<PY, PZ>(eb, 2 * CS + x0 + PY * y0 + PZ * zh);
+    E[1] = interp_pairs(b, st.f0[0], st.fh[1], st.f0[2]);
+    b = ld_pair4<PY, PZ>(eb, 3 * CS + x0 + PY * yh + PZ * zh);
+    E[2] = interp_pairs(a, st.f0[0], st.f0[1], st.fh[2]);
+    a = ld_pair4<PY, PZ>(eb, 4 * CS + xh + PY * y0 + PZ * zh);
+    B[0] = interp_pairs(b, st.f0[0], st.fh[1], st.fh[2]);
+    b = ld_pair4<PY, PZ>(eb, 5 * CS + xh + PY * yh + PZ * z0);
+    B[1] = interp_pairs(a, st.fh[0], st.f0[1], st.fh[2]);
+    B[2] = interp_pairs(b, st.fh[0], st.fh[1], st.f0[2]);
 }
 
 // Gather of the six components from the global FP64 arrays (far movers);
@@ -410,7 +428,7 @@ push_mixed_kernel(const MArgs a) {
     constexpr int JPY = L::JPY, JPZ = L::JPZ, JC = L::JC;
     constexpr int kWaves = kBlock / 64;
     constexpr int QCAP = 28;
-    __shared__ float eb[6 * L::ECS];
+    __shared__ __attribute__((aligned(16))) float eb[6 * L::ECS];
     // J tile: FP64 sums, or (DET) 64-bit hi sums followed by 32-bit lo sums
     constexpr int JT_BYTES = DET ? 3 * JC * 12 : 3 * JC * 8;
     __shared__ __attribute__((aligned(16))) unsigned char jraw[JT_BYTES];
@@ -472,14 +490,29 @@ push_mixed_kernel(const MArgs a) {
         if (ip < p1) ld7(ip, ncell, nxt);
     }
 
+    // tile of x-pairs: the values first (the last node of a row in the
+    // difference slot of the pair before it), then the differences
     for (int r = threadIdx.x; r < T3; r += kBlock) {
         const int tz = r / T2, ty = (r / T) % T, tx = r % T;
         const int gi = tile_node_index(org, tx, ty, tz, nx, ny, nz, near);
-        const int li = tx + L::EPY * ty + L::EPZ * tz;
+        const int li = (tx < T - 1 ? 2 * tx : 2 * T - 3) + L::EPY * ty + L::EPZ * tz;
 #pragma unroll
         for (int c = 0; c < 6; ++c) eb[c * L::ECS + li] = (float)a.EB[c][gi];
     }
     for (int t = threadIdx.x; t < JT_BYTES / 4; t += kBlock) ((int*)jraw)[t] = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < T3; r += kBlock) {
+        const int tz = r / T2, ty = (r / T) % T, tx = r % T;
+        if (tx < T - 1) {
+            const int li = 2 * tx + L::EPY * ty + L::EPZ * tz;
+            const int ln = tx < T - 2 ? li + 2 : li + 1;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const float v0 = eb[c * L::ECS + li], v1 = eb[c * L::ECS + ln];
+                eb[c * L::ECS + li + 1] = v1 - v0;
+            }
+        }
+    }
     __syncthreads();
 
     // relative cell of c inside the tile window [-H, S+H), periodic

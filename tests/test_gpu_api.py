@@ -146,8 +146,10 @@ def test_timers_and_counters():
     assert t[7] >= t[0] + t[2] + t[5] and t[9] == 0
     c = sim.counters()
     assert c[1] == 1 and c[2] == 25
-    # E/B tile 8^3 x 6, padded J tile 3 x 1001, crosser queues 8 waves x 6 x 28 doubles
-    assert c[3] == (6 * 544 + 3 * 1001 + 8 * 6 * 28) * 8    # E/B tile, J tile, crosser queues
+    # E/B tile of x-pairs (8 z-planes of 8 rows of 7 pairs, plane pitch padded
+    # from 112 to 116 doubles) x 6, padded J tile 3 x 1001, crosser queues
+    # 8 waves x 6 x 28 doubles
+    assert c[3] == (6 * 116 * 8 + 3 * 1001 + 8 * 6 * 28) * 8
     # mode 2: only the stored-order push+deposit kernel is bracketed
     pic.pic_enable_timers(sim.ctx, 2)
     sim.step(5)
