@@ -188,7 +188,10 @@ int pic_diagnostics(pic_ctx* ctx, double out[8]);
  * pic_enable_timers(ctx, mode) resets them and sets the mode: 0 off, 1 every
  * stage below, 2 only the push+deposit kernel in stored order (ms[0]; one
  * event pair per step, which keeps the timing overhead out of the other
- * stages).  Other modes: PIC_EINVAL. */
+ * stages), 3 as 2 on the timed steps 0, 7, 14, ... only (ms[1] counts the
+ * launches bracketed; an event pair holds the stream for several
+ * microseconds, so sampling keeps that cost out of the step time).  Other
+ * modes: PIC_EINVAL. */
 int pic_enable_timers(pic_ctx* ctx, int32_t mode);
 
 /* Milliseconds summed over the timed steps, and launch counts:

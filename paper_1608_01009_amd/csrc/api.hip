@@ -120,7 +120,8 @@ struct pic_ctx {
     int64_t steps = 0;
     int steps_since_sort = 0;
     int64_t rebins = 0;
-    int timers = 0;        // 0 off, 1 every stage, 2 the stored-order push+deposit kernel only
+    int timers = 0;        // 0 off, 1 every stage, 2 the stored-order push+deposit kernel only,
+                           // 3 that kernel on one timed step in seven
     double t_ms[ST_N] = {};
     int64_t push_launches = 0;       // push+deposit launches in stored order
     int64_t push_perm_launches = 0;  // push+deposit launches reading through a re-sort order
@@ -210,13 +211,23 @@ hipEvent_t take_event(pic_ctx* c) {
     return e;
 }
 
+// Timer mode 3 brackets the stored-order push of one timed step in
+// kPushSampleStride (7, coprime with the usual re-sort periods, so that the
+// samples fall on every step of a period in turn).  An event pair costs the
+// stream about 5.6 us on each side of the bracketed kernel.
+constexpr int64_t kPushSampleStride = 7;
+
+bool push_sampled(const pic_ctx* c) {
+    return c->timers != 3 || c->timed_steps % kPushSampleStride == 0;
+}
+
 // Brackets a launch sequence with events when timers are on.
 struct Timed {
     pic_ctx* c;
     int stage;
     hipEvent_t a = nullptr;
     Timed(pic_ctx* c_, int st) : c(c_), stage(st) {
-        if (c->timers == 1 || (c->timers == 2 && st == ST_PUSH)) {
+        if (c->timers == 1 || (c->timers >= 2 && st == ST_PUSH && push_sampled(c))) {
             a = take_event(c);
             if (a) (void)hipEventRecord(a, c->stream);
         }
@@ -423,7 +434,7 @@ int step_once(pic_ctx* c) {
                                             c->det, c->stream));
         }
         c->pair_phase = 1 - c->pair_phase;
-        if (c->timers) (pend ? c->push_perm_launches : c->push_launches)++;
+        if (c->timers && (pend || push_sampled(c))) (pend ? c->push_perm_launches : c->push_launches)++;
         if (pend) {
             Timed t(c, ST_SORT);
             for (int k = 0; k < 2; ++k) {
@@ -481,7 +492,8 @@ int step_once(pic_ctx* c) {
                                             c->det, c->stream));
         }
         c->far_phase = 1 - c->far_phase;
-        if (c->timers) (s.pending ? c->push_perm_launches : c->push_launches)++;
+        if (c->timers && (s.pending || push_sampled(c)))
+            (s.pending ? c->push_perm_launches : c->push_launches)++;
         if (s.pending) {
             Timed t(c, ST_SORT);
             HIPCHK(c, launch_permute_ids(s.n, s.perm, mixed ? srcm.id : src.id,
@@ -1385,7 +1397,7 @@ int pic_enable_timers(pic_ctx* c, int32_t on) {
     c->err.clear();
     (void)hipStreamSynchronize(c->stream);
     collect_timers(c);
-    if (on < 0 || on > 2) return fail(c, PIC_EINVAL, "timer mode must be 0, 1 or 2");
+    if (on < 0 || on > 3) return fail(c, PIC_EINVAL, "timer mode must be 0, 1, 2 or 3");
     c->timers = on;
     for (int k = 0; k < ST_N; ++k) c->t_ms[k] = 0.0;
     c->push_launches = 0;

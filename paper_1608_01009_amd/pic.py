@@ -235,7 +235,8 @@ def pic_diagnostics(ctx) -> np.ndarray:
 
 
 def pic_enable_timers(ctx, on=True):
-    """on: False/0 off, True/1 every stage, 2 the stored-order push+deposit only."""
+    """on: False/0 off, True/1 every stage, 2 the stored-order push+deposit only,
+    3 that kernel on one timed step in seven."""
     _check(ctx, library().pic_enable_timers(ctx, int(on)))
 
 

@@ -156,8 +156,15 @@ def test_timers_and_counters():
     t = pic.pic_get_timers(sim.ctx)
     assert t[0] > 0 and t[1] == 5 and t[8] == 5
     assert t[2] == 0 and t[4] == 0 and t[5] == 0 and t[6] == 0 and t[7] == 0
+    # mode 3: that kernel on the timed steps 0, 7, 14 only (the re-sort after
+    # step 40 falls between the samples)
+    pic.pic_enable_timers(sim.ctx, 3)
+    sim.step(15)
+    t = pic.pic_get_timers(sim.ctx)
+    assert t[0] > 0 and t[1] == 3 and t[8] == 15
+    assert t[2] == 0 and t[4] == 0 and t[5] == 0 and t[6] == 0 and t[7] == 0
     with pytest.raises(pic.PicError) as ei:
-        pic.pic_enable_timers(sim.ctx, 3)
+        pic.pic_enable_timers(sim.ctx, 4)
     assert ei.value.code == pic.PIC_EINVAL
     sim.close()
 
