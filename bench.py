@@ -10,7 +10,8 @@ timed region starts.
 
 Prints one JSON line with the throughput (particle updates/s), the roofline
 of the dominant kernel (push+deposit, HBM-bound: algorithmic bytes per launch
-over its average duration measured with HIP events on the library's stream),
+over its average duration measured with HIP events on the library's stream, on
+one timed step in seven),
 the oracle's throughput on the host as a reported CPU baseline, and under
 "fp32_mixed" the same measurement of the mixed-precision variant
 (PIC_FP32_MIXED: integer cell + FP32 offsets and momenta, FP64 fields and J)
@@ -419,7 +420,8 @@ def main():
         other.close()
     value = n * args.steps / wall
     # the dominant kernel: push+deposit reading the particles in stored order
-    # (19 of every 20 steps); its HIP events bracket that kernel alone
+    # (19 of every 20 steps); its HIP events bracket that kernel alone, on the
+    # sampled steps
     push_ms_avg = tm[0] / max(tm[1], 1)
     bytes_launch = algorithmic_bytes_per_launch(n, wl.ncells)
     achieved = bytes_launch / (push_ms_avg * 1e-3) / 1e9
